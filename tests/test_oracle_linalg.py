@@ -1,0 +1,159 @@
+"""Pins of the oracle's Householder QR, Cholesky-QR pieces, ICE and metrics."""
+import mpmath
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle import householder as HH, cholqr as CQ, condest as CE, metrics as MT
+import workloads as W
+
+
+def _lapack_qr(A):
+    q, r = np.linalg.qr(A)
+    d = np.sign(np.diag(r))
+    d[d == 0] = 1
+    return q * d[None, :], r * d[:, None]
+
+
+@pytest.mark.parametrize("m,n", [(50, 7), (300, 32), (64, 64)])
+def test_householder_matches_lapack(m, n):
+    A = W.test_matrix(m, n, 1e3, m + n)
+    Q, R = HH.householder_qr(A)
+    Ql, Rl = _lapack_qr(A)
+    assert np.max(np.abs(R - Rl)) < 1e-12 * np.abs(Rl).max()
+    assert np.max(np.abs(Q - Ql)) < 1e-10
+    assert np.all(np.diag(R) > 0)
+    assert MT.orthogonality(Q) < 1e-14
+
+
+def test_householder_matches_mpmath_gram_schmidt_tiny():
+    mpmath.mp.dps = 50
+    A = W.gaussian(9, 4, 11)
+    M = mpmath.matrix(A.tolist())
+    # modified Gram-Schmidt in 50 digits = exact thin QR (diag(R) > 0)
+    m, n = A.shape
+    Q = [[M[i, j] for i in range(m)] for j in range(n)]
+    R = mpmath.matrix(n, n)
+    for j in range(n):
+        for k in range(j):
+            R[k, j] = mpmath.fsum(Q[k][i] * Q[j][i] for i in range(m))
+            Q[j] = [Q[j][i] - R[k, j] * Q[k][i] for i in range(m)]
+        R[j, j] = mpmath.sqrt(mpmath.fsum(x * x for x in Q[j]))
+        Q[j] = [x / R[j, j] for x in Q[j]]
+    Rx = np.array([[float(R[i, j]) for j in range(n)] for i in range(n)])
+    Qx = np.array([[float(Q[j][i]) for j in range(n)] for i in range(m)])
+    Qh, Rh = HH.householder_qr(A)
+    assert np.max(np.abs(Rh - Rx)) < 1e-14 * np.abs(Rx).max()
+    assert np.max(np.abs(Qh - Qx)) < 1e-14
+
+
+def test_householder_float32_within_backward_bound():
+    A = W.test_matrix(200, 16, 1e2, 3)
+    _, R32 = HH.householder_qr(A.astype(np.float32), dtype=np.float32)
+    _, R64 = HH.householder_qr(A.astype(np.float32).astype(np.float64))
+    assert R32.dtype == np.float32
+    rel = np.linalg.norm(R32 - R64) / np.linalg.norm(R64)
+    assert rel < 50 * 16 * 2.0 ** -24 * 1e2
+
+
+def test_householder_zero_column_below_diagonal():
+    A = np.zeros((6, 3))
+    A[0, 0], A[1, 1], A[2, 2] = -2.0, 3.0, -1.0
+    Q, R = HH.householder_qr(A)
+    assert np.allclose(R, np.diag([2.0, 3.0, 1.0]))
+    assert np.allclose(Q @ R, A)
+
+
+def test_trsm_matches_scipy():
+    A = W.gaussian(500, 20, 5)
+    R = W.upper_triangular(20, 1e6, 6)
+    X = CQ.trsm_right_upper(A, R)
+    ref = scipy.linalg.solve_triangular(R, A.T, trans="T", lower=False).T
+    assert np.max(np.abs(X - ref)) < 1e-9 * np.abs(ref).max()
+    assert np.max(np.abs(X @ R - A)) < 1e-12 * np.abs(A).max() * 20
+
+
+def test_cholesky_matches_numpy():
+    G = W.spd_matrix(40, 1e6, 7)
+    R = CQ.cholesky_upper(G)
+    L = np.linalg.cholesky(G)
+    assert np.max(np.abs(R - L.T)) < 1e-12 * np.abs(L).max() * 1e3
+    assert np.allclose(np.triu(R), R)
+
+
+@pytest.mark.parametrize("j", [0, 3, 7])
+def test_cholesky_breakdown_index(j):
+    G = np.eye(8)
+    G[j, j] = -1.0
+    with pytest.raises(CQ.CholeskyBreakdown) as e:
+        CQ.cholesky_upper(G)
+    assert e.value.index == j
+
+
+def test_cholesky_breakdown_on_exactly_singular_gram():
+    # [[4,2,0],[2,1,0],[0,0,1]]: r00 = 2, r01 = 1, second pivot 1 - 1 = 0 exactly
+    G = np.array([[4.0, 2.0, 0.0], [2.0, 1.0, 0.0], [0.0, 0.0, 1.0]])
+    with pytest.raises(CQ.CholeskyBreakdown) as e:
+        CQ.cholesky_upper(G)
+    assert e.value.index == 1
+    # indefinite: second pivot 1 - 4 = -3
+    with pytest.raises(CQ.CholeskyBreakdown) as e:
+        CQ.cholesky_upper(np.array([[1.0, 2.0], [2.0, 1.0]]))
+    assert e.value.index == 1
+
+
+def test_trmm_upper():
+    R1 = W.upper_triangular(10, 10, 1)
+    R2 = W.upper_triangular(10, 10, 2)
+    assert np.allclose(CQ.trmm_upper(R1, R2), R1 @ R2)
+
+
+def test_ice_exact_for_two_by_two_and_diagonal():
+    R = np.array([[3.0, -1.5], [0.0, 0.25]])
+    sv = np.linalg.svd(R, compute_uv=False)
+    assert abs(CE.sigma_max_est(R) - sv[0]) < 1e-14 * sv[0]
+    assert abs(CE.sigma_min_est(R) - sv[1]) < 1e-13 * sv[1]
+    D = np.diag([5.0, 1e-3, 2.0, 7.0])
+    assert abs(CE.kappa_est(D) - 7.0 / 1e-3) < 1e-9
+
+
+@pytest.mark.parametrize("kappa", [1e2, 1e6, 1e12])
+def test_ice_brackets_and_is_close(kappa):
+    R = W.upper_triangular(64, kappa, 9)
+    sv = np.linalg.svd(R, compute_uv=False)
+    smax, smin = CE.sigma_max_est(R), CE.sigma_min_est(R)
+    assert smax <= sv[0] * (1 + 1e-12) and smin >= sv[-1] * (1 - 1e-9)
+    k = CE.kappa_est(R)
+    assert kappa / 30 < k <= (sv[0] / sv[-1]) * (1 + 1e-9)
+
+
+def test_ice_singular():
+    R = np.triu(np.ones((4, 4)))
+    R[2, 2] = 0.0
+    R[2, 3] = 0.0
+    R[3, 3] = 0.0
+    assert CE.kappa_est(R) == float("inf") or CE.kappa_est(R) > 1e15
+
+
+def test_orthogonality_metric_vs_mpmath():
+    mpmath.mp.dps = 40
+    Q, _ = np.linalg.qr(W.gaussian(30, 3, 12))
+    Q[0, 0] += 1e-12
+    Qm = mpmath.matrix(Q.tolist())
+    E = mpmath.eye(3) - Qm.T * Qm
+    ev = mpmath.eigsy(0.5 * (E + E.T))[0]
+    ref = max(abs(float(v)) for v in ev)
+    assert abs(MT.orthogonality(Q, chunk=7) - ref) < 1e-15
+
+
+def test_orthogonality_accurate_for_long_columns():
+    m = 1 << 19
+    u, _, _ = W.test_matrix_factors(m, 4, 1.0, 13)
+    assert MT.orthogonality(u) < 5e-15
+
+
+def test_residual_metric():
+    A = W.test_matrix(100, 5, 10.0, 14)
+    Q, R = np.linalg.qr(A)
+    assert MT.residual(A, Q, R) < 1e-14
+    assert abs(MT.residual(A, Q, R * 1.001) - 1e-3 * np.linalg.norm(R, 2) / np.linalg.norm(A, 2)) < 1e-6

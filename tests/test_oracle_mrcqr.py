@@ -1,0 +1,180 @@
+"""Pins of the oracle's full MRCQR (Algorithm 2) against facts fixed by the
+mathematics: uniqueness of the thin QR, the construction's singular values,
+Theorem 1, and the paper's stated precision regimes."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import mrcqr as M, precision as P, metrics as MT, householder as HH
+from oracle import condest as CE
+import workloads as W
+from conftest import GOLDEN
+
+CLAIMS = json.load(open(os.path.join(GOLDEN, "paper_claims.json")))
+m, n = 4096, 32
+
+
+@pytest.fixture(scope="module")
+def mats():
+    return {k: W.test_matrix(m, n, k, 21) for k in [1e2, 1e4, 1e8, 1e12, 1e16]}
+
+
+@pytest.mark.parametrize("kappa", [1e2, 1e4, 1e8])
+def test_fp64_matches_unique_householder_qr(mats, kappa):
+    A = mats[kappa]
+    r = M.factor(A, P.FP64, seed=1)
+    Qh, Rh = M.reference_qr(A)
+    tol = 50 * n * 2.0 ** -53 * kappa
+    assert MT.rel_diff(r.R, Rh) < tol
+    assert np.max(np.abs(r.Q - Qh)) < tol
+
+
+@pytest.mark.parametrize("kappa", [1e2, 1e4, 1e8, 1e12, 1e16])
+def test_fp64_sketch_orthogonality_and_residual(mats, kappa):
+    A = mats[kappa]
+    r = M.factor(A, P.FP64, seed=2)
+    assert r.status == M.STATUS_OK
+    assert MT.orthogonality(r.Q) < CLAIMS["orthogonality_fp64_sketch_all_kappa"] * 4
+    assert MT.residual(A, r.Q, r.R, 1.0) < CLAIMS["target_residual"]
+
+
+@pytest.mark.parametrize("prec,kappa", [(P.FP16, 1e2), (P.FP16, 1e4), (P.FP32, 1e4), (P.FP32, 1e8),
+                                        (P.BF16, 1e2)])
+def test_low_precision_inside_regime(mats, prec, kappa):
+    A = mats[kappa]
+    r = M.factor(A, prec, seed=3)
+    assert r.status == M.STATUS_OK
+    assert MT.orthogonality(r.Q) < CLAIMS["target_orthogonality"]
+    assert MT.residual(A, r.Q, r.R, 1.0) < CLAIMS["target_residual"]
+
+
+@pytest.mark.parametrize("prec,kappa", [(P.FP16, 1e8), (P.FP32, 1e12)])
+def test_low_precision_outside_regime_degrades_and_is_flagged(mats, prec, kappa):
+    A = mats[kappa]
+    r = M.factor(A, prec, seed=4)
+    if r.Q is None:
+        assert r.status in (M.STATUS_CHOL_BREAKDOWN, M.STATUS_SKETCH_SINGULAR)
+        return
+    assert MT.orthogonality(r.Q) > 1e-12
+    assert r.status == M.STATUS_POSTERIOR_WARN
+    assert MT.residual(A, r.Q, r.R, 1.0) < 1e-13  # still backward stable
+
+
+def test_singular_values_of_r_are_the_constructed_ones(mats):
+    A = mats[1e4]
+    r = M.factor(A, P.FP16, seed=5)
+    sv = np.linalg.svd(r.R, compute_uv=False)
+    sig = W.singular_values(n, 1e4)
+    assert np.max(np.abs(sv - sig)) < 100 * n * 2.0 ** -53
+
+
+def test_kappa_one_gives_identity_r():
+    U, _, _ = W.test_matrix_factors(2048, 16, 1.0, 6)
+    r = M.factor(U, P.FP32, seed=7)
+    assert np.max(np.abs(r.R - np.eye(16))) < 1e-14
+    assert np.max(np.abs(r.Q - U)) < 1e-14
+
+
+@pytest.mark.parametrize("prec", [P.FP64, P.FP32])
+def test_power_of_two_scaling_is_exact(mats, prec):
+    A = mats[1e4]
+    r1 = M.factor(A, prec, seed=8)
+    r2 = M.factor(A * 2.0 ** 37, prec, seed=8)
+    assert np.array_equal(r2.R, r1.R * 2.0 ** 37)
+    assert np.array_equal(r2.Q, r1.Q)
+
+
+def test_seed_and_precision_invariance(mats):
+    A = mats[1e4]
+    Rs = [M.factor(A, p, seed=sd).R for p, sd in [(P.FP64, 1), (P.FP64, 99), (P.FP16, 5), (P.FP32, 6)]]
+    for R in Rs[1:]:
+        assert MT.rel_diff(R, Rs[0]) < 1e-11
+
+
+def _cond(X):
+    sv = np.linalg.svd(X, compute_uv=False)
+    return sv[0] / sv[-1]
+
+
+def _theorem1_terms(A, prec):
+    _, _, _, Rs = M.stage1(A, P.FP64, 9, 2 * n)
+    _, _, _, Rh = M.stage1(A, prec, 9, 2 * n)
+    k_rs = _cond(Rs)
+    eps = np.linalg.norm(Rh - Rs, 2) / np.linalg.norm(Rs, 2)
+    k_hat = _cond(np.linalg.solve(Rh.T, A.T).T)
+    k_one = _cond(np.linalg.solve(Rs.T, A.T).T)
+    return eps * k_rs, k_hat, k_one
+
+
+@pytest.mark.parametrize("prec,kappa", [(P.FP16, 1e2), (P.FP16, 1e3), (P.FP32, 1e4), (P.FP32, 1e6),
+                                        (P.BF16, 1e2)])
+def test_theorem1_bound_holds(prec, kappa):
+    # Theorem 1: with E = Rs_hat - Rs and eps = ||E|| / ||Rs||, if eps*kappa(Rs) < 1
+    # then kappa(A Rs_hat^-1) <= kappa(A Rs^-1) (1 + eps k) / (1 - eps k).
+    A = W.test_matrix(m, n, kappa, 21)
+    ek, k_hat, k_one = _theorem1_terms(A, prec)
+    assert ek < 1
+    assert k_hat <= k_one * (1 + ek) / (1 - ek) * (1 + 1e-6)
+    assert k_hat < 50
+
+
+def test_theorem1_is_sufficient_not_necessary_at_fp16_edge(mats):
+    # at the paper's FP16 regime bound (1e4) the hypothesis eps*kappa < 1 fails,
+    # yet the preconditioned matrix stays well conditioned
+    ek, k_hat, _ = _theorem1_terms(mats[1e4], P.FP16)
+    assert ek > 1
+    assert k_hat < 50
+
+
+def test_preconditioned_matrix_is_well_conditioned(mats):
+    A = mats[1e12]
+    _, _, _, Rs = M.stage1(A, P.FP64, 10, 2 * n)
+    sv = np.linalg.svd(np.linalg.solve(Rs.T, A.T).T, compute_uv=False)
+    assert sv[0] / sv[-1] < 20  # about (1 + sqrt(1/2)) / (1 - sqrt(1/2)) = 5.8 for s = 2n
+
+
+def test_all_rows_sketch_gives_exact_r():
+    # s = m: the sketch operator is orthogonal, so Rs = R(A) and R2 = I
+    A = W.test_matrix(256, 8, 1e6, 11)
+    r = M.factor(A, P.FP64, seed=12, s=256, keep=True)
+    _, Rh = HH.householder_qr(A)
+    assert MT.rel_diff(r.intermediates["Rs"], Rh) < 1e-9
+    assert np.max(np.abs(r.intermediates["Rc"] - np.eye(8))) < 1e-9
+
+
+@pytest.mark.parametrize("kappa,expect", [(1e2, P.FP16), (1e8, P.FP32), (1e16, P.FP64)])
+def test_auto_policy_lands_in_the_papers_regime(mats, kappa, expect):
+    A = mats[kappa]
+    r = M.factor(A, M.AUTO, seed=13)
+    assert r.status == M.STATUS_OK
+    assert r.precision_used == expect
+    assert MT.orthogonality(r.Q) < CLAIMS["target_orthogonality"]
+
+
+def test_zero_column_gives_singular_sketch():
+    A = W.gaussian(512, 6, 14)
+    A[:, 3] = 0.0
+    for prec in [P.FP64, P.FP16]:
+        r = M.factor(A, prec, seed=15)
+        assert r.status == M.STATUS_SKETCH_SINGULAR and r.Q is None
+
+
+def test_numerically_rank_deficient_input_still_backward_stable():
+    # a duplicated column leaves Rs with a pivot at rounding level; the result
+    # is a backward-stable QR with orthonormal Q (as Householder QR would give)
+    A = W.gaussian(512, 6, 14)
+    A[:, 5] = A[:, 2]
+    r = M.factor(A, P.FP64, seed=15)
+    assert r.kappa_rs > 1e14
+    if r.Q is not None:
+        assert MT.orthogonality(r.Q) < 1e-13
+        assert MT.residual(A, r.Q, r.R) < 1e-14
+
+
+def test_ice_estimate_tracks_kappa_of_sketch_factor(mats):
+    for kappa in [1e2, 1e4, 1e8]:
+        _, _, _, Rs = M.stage1(mats[kappa], P.FP64, 16, 2 * n)
+        k = CE.kappa_est(Rs)
+        assert kappa / 20 < k <= kappa * 1.01
