@@ -157,3 +157,41 @@ def test_residual_metric():
     Q, R = np.linalg.qr(A)
     assert MT.residual(A, Q, R) < 1e-14
     assert abs(MT.residual(A, Q, R * 1.001) - 1e-3 * np.linalg.norm(R, 2) / np.linalg.norm(A, 2)) < 1e-6
+
+
+def _ice_mpmath(R, largest):
+    """ICE with the 2x2 eigenproblem solved by mpmath in 60 digits."""
+    mpmath.mp.dps = 60
+    n = R.shape[0]
+    est = mpmath.mpf(abs(R[0, 0]))
+    x = [mpmath.mpf(1)]
+    for j in range(1, n):
+        alpha = mpmath.fsum(mpmath.mpf(R[i, j]) * x[i] for i in range(j))
+        gamma = mpmath.mpf(R[j, j])
+        M = mpmath.matrix([[est ** 2 + alpha ** 2, alpha * gamma], [alpha * gamma, gamma ** 2]])
+        ev, Q = mpmath.eigsy(M)
+        idx = (1 if ev[1] > ev[0] else 0) if largest else (0 if ev[0] < ev[1] else 1)
+        s, c = Q[0, idx], Q[1, idx]
+        x = [s * xi for xi in x] + [c]
+        est = mpmath.sqrt(max(ev[idx], 0))
+    return float(est)
+
+
+@pytest.mark.parametrize("kappa", [1e3, 1e16])
+def test_ice_closed_form_matches_high_precision(kappa):
+    R = W.upper_triangular(24, kappa, 17)
+    for largest in (True, False):
+        want = _ice_mpmath(R, largest)
+        got = CE._ice(R, largest)
+        assert abs(got - want) <= 1e-10 * want
+
+
+def test_ice_step_eigenpair_definition():
+    for est, a, g in [(1.0, 0.3, 2.0), (1e-9, 1.0, 1e-9), (2.0, 0.0, 2.0), (0.5, -3.0, 0.25)]:
+        M = np.array([[est * est + a * a, a * g], [a * g, g * g]])
+        for largest in (True, False):
+            s, c, e2 = CE.ice_step(est, a, g, largest)
+            lam = e2 * e2
+            v = np.array([s, c])
+            assert abs(np.hypot(s, c) - 1) < 1e-15
+            assert np.linalg.norm(M @ v - lam * v) <= 1e-14 * max(1.0, np.abs(M).max())
