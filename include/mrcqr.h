@@ -1,0 +1,186 @@
+/*
+ * mrcqr.h - C ABI of the MI355X (gfx950) MRCQR library.
+ *
+ * MRCQR computes the thin QR factorization A = Q R of a tall-skinny float64
+ * matrix A (m x n, m >= n, rank n) with an explicit Q (Q^T Q = I_n) and an
+ * upper-triangular R with positive diagonal. It follows Algorithm 2 of
+ * Garrison, Chen and Ipsen, "Numerically Stable Cholesky-QR on GPU via
+ * Mixed-Precision Randomized Preconditioning" (arXiv 2606.18411):
+ *   Stage 1 (sketch precision p): Rademacher signs D, a subsampled DCT-II
+ *           along the rows (the sketch Y = S F D A, s rows), Householder QR
+ *           of Y giving the preconditioner Rs;
+ *   Stage 2 (float64): B = A Rs^{-1}, then Cholesky-QR of B (Algorithm 1):
+ *           G = B^T B, G = Rc^T Rc, Q = B Rc^{-1};
+ *   Stage 3: R = Rc Rs.
+ *
+ * Conventions for every entry point:
+ *   - all matrices are column-major float64 with a leading dimension
+ *     (element (i, j) of X is X[i + j * ldx]); ld >= number of rows;
+ *   - every matrix/array pointer is a DEVICE pointer (hipMalloc'd or
+ *     torch-allocated memory on the current device); the library never
+ *     frees or retains caller memory past the call;
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream); all
+ *     work is enqueued asynchronously on it; nothing synchronizes;
+ *   - argument errors are returned synchronously (MRCQR_ERR_ARG /
+ *     MRCQR_ERR_UNSUPPORTED) before anything is launched; numeric outcomes
+ *     (Cholesky breakdown, singular sketch, posterior warning) are written
+ *     asynchronously to a device-resident mrcqr_info that the caller reads
+ *     after synchronizing the stream;
+ *   - results are deterministic: the same inputs, seed and device give
+ *     bitwise-identical outputs (no floating-point atomics).
+ * Limits of this build: 1 <= n <= 128, n <= s <= m, s * n <= 65536,
+ * m < 2^28.
+ */
+#ifndef MRCQR_H
+#define MRCQR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Sketch precision p of Algorithm 2 (Section "Adaptive Precision
+ * Selection": half for kappa < 1e4, single below 1e8, double otherwise).
+ * BF16 is an extra option (8-bit exponent, 8-bit significand).
+ * AUTO starts at FP16 and escalates per call from an on-device condition
+ * estimate of Rs (see mrcqr_factor). */
+enum mrcqr_precision {
+  MRCQR_PREC_AUTO = 0,
+  MRCQR_PREC_FP64 = 1,
+  MRCQR_PREC_FP32 = 2,
+  MRCQR_PREC_FP16 = 3,
+  MRCQR_PREC_BF16 = 4
+};
+
+enum mrcqr_status {
+  MRCQR_OK = 0,
+  MRCQR_ERR_ARG = 1,              /* invalid argument (synchronous)               */
+  MRCQR_ERR_NONFINITE = 2,        /* non-finite value met in the sketch           */
+  MRCQR_ERR_CHOL_BREAKDOWN = 3,   /* Gram matrix not numerically SPD (Algorithm 1
+                                     breakdown); chol_fail_index = first pivot   */
+  MRCQR_ERR_SKETCH_SINGULAR = 4,  /* Rs has a zero or non-finite diagonal entry   */
+  MRCQR_ERR_WORKSPACE = 5,        /* workspace missing or too small (synchronous) */
+  MRCQR_ERR_DEVICE = 6,           /* a HIP runtime call failed (synchronous)      */
+  MRCQR_WARN_POSTERIOR = 7,       /* Q, R produced, but the estimate of
+                                     kappa(Rc) exceeds the posterior bound: the
+                                     sketch precision was too low for A (Section
+                                     "Adaptive Precision Selection", rerun rule)  */
+  MRCQR_ERR_UNSUPPORTED = 8       /* shape outside this build's limits (synchronous) */
+};
+
+/* Per-call outcome, written by the device at the end of the call. */
+typedef struct mrcqr_info {
+  int32_t status;          /* mrcqr_status                                     */
+  int32_t precision_used;  /* mrcqr_precision of the accepted Stage 1          */
+  int32_t chol_fail_index; /* first failing pivot, or -1                       */
+  int32_t escalations;     /* AUTO: number of precision escalations            */
+  double kappa_rs_est;     /* ICE estimate of kappa_2(Rs) (a lower bound)      */
+  double kappa_rc_est;     /* ICE estimate of kappa_2(Rc) = kappa_2(B)         */
+} mrcqr_info;
+
+typedef struct mrcqr_plan mrcqr_plan;
+
+/* ---------------------------------------------------------------------
+ * Whole factorization (Algorithm 2, all three stages).
+ *
+ * A (m x n, lda) is read only. Q (m x n, ldq) and R (n x n, ldr; the strict
+ * lower triangle is set to zero) are written. Q must not overlap A.
+ * s: sketch rows (0 = default 2n); n <= s <= m.
+ * seed: selects D and S (counter-based SplitMix64 draw, Floyd sampling).
+ * info_dev: device pointer to one mrcqr_info (may be NULL).
+ * The workspace comes from a per-device cache keyed by (m, n, s), created
+ * on first use with hipMalloc; use the plan API to supply it yourself.
+ * AUTO: Stage 1 runs in FP16; if the ICE estimate of kappa(Rs) is >= 1e4
+ * it is redone in FP32, and if that estimate is >= 1e8, in FP64. The
+ * decision is taken on the device (no host round trip).
+ * Returns MRCQR_OK when the work was enqueued.
+ * ------------------------------------------------------------------- */
+int mrcqr_factor(const double* A, int64_t m, int64_t n, int64_t lda,
+                 int sketch_precision, uint64_t seed, int64_t s,
+                 double* Q, int64_t ldq, double* R, int64_t ldr,
+                 void* stream, mrcqr_info* info_dev);
+
+/* Plan API: a plan fixes (m, n, s); execute allocates nothing. */
+int mrcqr_plan_create(int64_t m, int64_t n, int64_t s, mrcqr_plan** out);
+size_t mrcqr_plan_workspace_bytes(const mrcqr_plan* plan);
+int mrcqr_execute(const mrcqr_plan* plan, void* workspace, size_t workspace_bytes,
+                  const double* A, int64_t lda, int sketch_precision, uint64_t seed,
+                  double* Q, int64_t ldq, double* R, int64_t ldr,
+                  void* stream, mrcqr_info* info_dev);
+int mrcqr_plan_destroy(mrcqr_plan* plan);
+
+/* Many independent factorizations (e.g. the repeated QRs of block Arnoldi
+ * or randomized SVD power steps). Per-instance arrays are HOST arrays of
+ * length `batch`; the matrices they point to are device memory. seeds[i]
+ * selects instance i's draw. infos_dev: device array of `batch` infos (or
+ * NULL). All instances are enqueued on `stream`. */
+int mrcqr_factor_batched(int32_t batch, const double* const* A, const int64_t* m,
+                         const int64_t* n, const int64_t* lda, const int32_t* precision,
+                         const uint64_t* seeds, double* const* Q, const int64_t* ldq,
+                         double* const* R, const int64_t* ldr,
+                         void* stream, mrcqr_info* infos_dev);
+
+/* ---------------------------------------------------------------------
+ * Individual steps of the path (same kernels as mrcqr_factor).
+ * ------------------------------------------------------------------- */
+
+/* Algorithm 2, Stage 1, first step: draw S (s distinct row indices of
+ * [0, m), sorted ascending, int32 S_dev[s]) and, if D_dev is not NULL, the
+ * Rademacher signs as int8 D_dev[m] in {+1, -1}. */
+int mrcqr_draw(uint64_t seed, int64_t m, int64_t s, int32_t* S_dev, int8_t* D_dev,
+               void* stream);
+
+/* Stage 1 DiagMult + transform + Select: Y (s x n, ldy, float64 storage)
+ * = gamma .* (C_p(S) * fl_p(D A)), C_p the DCT-II rows S rounded to p,
+ * gamma_0 = sqrt(1/s), gamma_k = sqrt(2/s); for p != FP64 the products are
+ * summed in float32 and Y holds float32 values. D is drawn from `seed`, S
+ * is read from S_dev (from mrcqr_draw). precision must not be AUTO.
+ * Needs mrcqr_sketch_workspace_bytes(m, n, s, precision) bytes of device
+ * workspace for the per-row-chunk partial sums. */
+size_t mrcqr_sketch_workspace_bytes(int64_t m, int64_t n, int64_t s, int precision);
+int mrcqr_sketch(const double* A, int64_t m, int64_t n, int64_t lda,
+                 const int32_t* S_dev, int64_t s, uint64_t seed, int precision,
+                 double* Y, int64_t ldy, void* workspace, size_t workspace_bytes,
+                 void* stream);
+
+/* Stage 1 SketchQR: Householder thin QR of Y (s x n) in float32
+ * (qr_precision = FP32) or float64 (FP64); Rs (n x n, upper, diag > 0,
+ * float64) and, if kappa_dev != NULL, the ICE estimate of kappa_2(Rs). */
+int mrcqr_sketch_qr(const double* Y, int64_t s, int64_t n, int64_t ldy, int qr_precision,
+                    double* Rs, int64_t ldr, double* kappa_dev, void* stream);
+
+/* Stage 2 triangular solve X = A R^{-1} (R upper, n x n), by blocked
+ * substitution (no inverse of R is formed). X must not overlap A. */
+int mrcqr_trsm(const double* A, int64_t m, int64_t n, int64_t lda,
+               const double* R, int64_t ldr, double* X, int64_t ldx, void* stream);
+
+/* Algorithm 1 step 1: G = B^T B (n x n, both triangles written). Needs
+ * mrcqr_gram_workspace_bytes(m, n) bytes of device workspace. */
+size_t mrcqr_gram_workspace_bytes(int64_t m, int64_t n);
+int mrcqr_gram(const double* B, int64_t m, int64_t n, int64_t ldb,
+               double* G, int64_t ldg, void* workspace, size_t workspace_bytes,
+               void* stream);
+
+/* Algorithm 1 step 2: G = Rc^T Rc, Rc upper (lower triangle zeroed).
+ * fail_dev (int32, may be NULL) receives -1 or the first failing pivot;
+ * kappa_dev (may be NULL) the ICE estimate of kappa_2(Rc). */
+int mrcqr_cholesky(const double* G, int64_t n, int64_t ldg, double* Rc, int64_t ldr,
+                   int32_t* fail_dev, double* kappa_dev, void* stream);
+
+/* Stage 3: R = R2 R1 for upper-triangular n x n factors. */
+int mrcqr_trmm(const double* R2, int64_t ld2, const double* R1, int64_t ld1,
+               int64_t n, double* R, int64_t ldr, void* stream);
+
+/* ICE condition estimate of an upper-triangular n x n matrix. */
+int mrcqr_condest(const double* R, int64_t n, int64_t ldr, double* kappa_dev, void* stream);
+
+const char* mrcqr_status_string(int status);
+/* Library version as major * 10000 + minor * 100 + patch. */
+int mrcqr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MRCQR_H */

@@ -1,0 +1,294 @@
+"""MRCQR on MI355X: mixed-precision randomized Cholesky-QR (arXiv 2606.18411).
+
+A thin Python binding over the C ABI of libmrcqr.so (include/mrcqr.h). It
+only marshals arguments: every step of the factorization runs in the HIP
+kernels of the library. PyTorch supplies device memory and the stream.
+
+Matrices are float64 CUDA tensors in column-major layout: shape (m, n) with
+stride (1, ld), ld >= m (e.g. ``torch.empty(n, m).t()``); ``colmajor()``
+converts.
+
+If the library is not built, or is built but cannot be loaded, every call
+raises RuntimeError; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import struct
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmrcqr.so")
+
+PREC = {"auto": 0, "fp64": 1, "fp32": 2, "fp16": 3, "bf16": 4}
+PREC_NAME = {v: k for k, v in PREC.items()}
+STATUS = {
+    0: "ok", 1: "invalid argument", 2: "non-finite sketch", 3: "cholesky breakdown",
+    4: "sketch singular", 5: "workspace", 6: "device error", 7: "posterior warning", 8: "unsupported",
+}
+OK, ERR_ARG, ERR_NONFINITE, ERR_CHOL, ERR_SINGULAR, ERR_WORKSPACE, ERR_DEVICE, WARN_POSTERIOR, ERR_UNSUPPORTED = range(9)
+
+_lib = None
+
+
+class MrcqrError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__(f"{where}: {STATUS.get(code, code)} (code {code})")
+        self.code = code
+
+
+def lib() -> ctypes.CDLL:
+    """Load libmrcqr.so (once); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run python -m paper_2606_18411_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        i64, u64, i32, vp, sz = ctypes.c_int64, ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p, ctypes.c_size_t
+        sig = {
+            "mrcqr_factor": (i32, [vp, i64, i64, i64, i32, u64, i64, vp, i64, vp, i64, vp, vp]),
+            "mrcqr_plan_create": (i32, [i64, i64, i64, ctypes.POINTER(vp)]),
+            "mrcqr_plan_workspace_bytes": (sz, [vp]),
+            "mrcqr_execute": (i32, [vp, vp, sz, vp, i64, i32, u64, vp, i64, vp, i64, vp, vp]),
+            "mrcqr_plan_destroy": (i32, [vp]),
+            "mrcqr_factor_batched": (i32, [ctypes.c_int32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
+            "mrcqr_draw": (i32, [u64, i64, i64, vp, vp, vp]),
+            "mrcqr_sketch_workspace_bytes": (sz, [i64, i64, i64, i32]),
+            "mrcqr_sketch": (i32, [vp, i64, i64, i64, vp, i64, u64, i32, vp, i64, vp, sz, vp]),
+            "mrcqr_sketch_qr": (i32, [vp, i64, i64, i64, i32, vp, i64, vp, vp]),
+            "mrcqr_trsm": (i32, [vp, i64, i64, i64, vp, i64, vp, i64, vp]),
+            "mrcqr_gram_workspace_bytes": (sz, [i64, i64]),
+            "mrcqr_gram": (i32, [vp, i64, i64, i64, vp, i64, vp, sz, vp]),
+            "mrcqr_cholesky": (i32, [vp, i64, i64, vp, i64, vp, vp, vp]),
+            "mrcqr_trmm": (i32, [vp, i64, vp, i64, i64, vp, i64, vp]),
+            "mrcqr_condest": (i32, [vp, i64, i64, vp, vp]),
+            "mrcqr_status_string": (ctypes.c_char_p, [i32]),
+            "mrcqr_version": (i32, []),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code: int, where: str) -> None:
+    if code != OK:
+        raise MrcqrError(code, where)
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _prec(p) -> int:
+    return PREC[p] if isinstance(p, str) else int(p)
+
+
+def colmajor(x: torch.Tensor) -> torch.Tensor:
+    """Column-major copy (stride (1, m)) of a 2-D tensor unless it already is one."""
+    if x.dim() != 2:
+        raise ValueError("expected a 2-D tensor")
+    if x.stride(0) == 1 and x.stride(1) >= max(1, x.shape[0]):
+        return x
+    return x.t().contiguous().t()
+
+
+def empty_colmajor(m: int, n: int, device="cuda", dtype=torch.float64) -> torch.Tensor:
+    return torch.empty((n, m), device=device, dtype=dtype).t()
+
+
+def _ld(x: torch.Tensor) -> int:
+    if x.dim() != 2 or x.stride(0) != 1:
+        raise ValueError("matrices must be column-major (stride(0) == 1)")
+    return max(x.stride(1), x.shape[0], 1)
+
+
+def _f64_cuda(x: torch.Tensor, name: str) -> None:
+    if not (x.is_cuda and x.dtype == torch.float64):
+        raise TypeError(f"{name} must be a float64 CUDA tensor")
+
+
+@dataclass
+class Info:
+    status: int
+    precision_used: int
+    chol_fail_index: int
+    escalations: int
+    kappa_rs_est: float
+    kappa_rc_est: float
+
+    @property
+    def precision(self) -> str:
+        return PREC_NAME.get(self.precision_used, str(self.precision_used))
+
+    @property
+    def ok(self) -> bool:
+        return self.status == OK
+
+    @staticmethod
+    def from_bytes(b: bytes) -> "Info":
+        return Info(*struct.unpack("<iiiidd", b))
+
+
+INFO_BYTES = 32
+
+
+def read_infos(buf: torch.Tensor, count: int = 1):
+    host = buf.cpu().numpy().tobytes()
+    return [Info.from_bytes(host[i * INFO_BYTES:(i + 1) * INFO_BYTES]) for i in range(count)]
+
+
+def factor(A: torch.Tensor, precision="fp16", seed: int = 0, s: int | None = None,
+           Q: torch.Tensor | None = None, R: torch.Tensor | None = None, stream=None,
+           sync: bool = True):
+    """Thin QR A = Q R by MRCQR. Returns (Q, R, Info) (Info None if sync=False)."""
+    _f64_cuda(A, "A")
+    m, n = A.shape
+    if Q is None:
+        Q = empty_colmajor(m, n, A.device)
+    if R is None:
+        R = empty_colmajor(n, n, A.device)
+    info = torch.empty(INFO_BYTES, dtype=torch.uint8, device=A.device)
+    code = lib().mrcqr_factor(A.data_ptr(), m, n, _ld(A), _prec(precision), seed & (2 ** 64 - 1), s or 0,
+                              Q.data_ptr(), _ld(Q), R.data_ptr(), _ld(R), _stream(stream), info.data_ptr())
+    _check(code, "mrcqr_factor")
+    if not sync:
+        return Q, R, info
+    torch.cuda.synchronize(A.device)
+    return Q, R, read_infos(info)[0]
+
+
+class Plan:
+    """A plan for fixed (m, n, s) with its own workspace; execute() allocates nothing."""
+
+    def __init__(self, m: int, n: int, s: int | None = None, device="cuda"):
+        p = ctypes.c_void_p()
+        _check(lib().mrcqr_plan_create(m, n, s or 0, ctypes.byref(p)), "mrcqr_plan_create")
+        self._p = p
+        self.m, self.n = m, n
+        self.workspace_bytes = int(lib().mrcqr_plan_workspace_bytes(p))
+        self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=device)
+        self.info = torch.empty(INFO_BYTES, dtype=torch.uint8, device=device)
+
+    def execute(self, A, Q, R, precision="fp16", seed: int = 0, stream=None):
+        _check(lib().mrcqr_execute(self._p, self.workspace.data_ptr(), self.workspace_bytes, A.data_ptr(), _ld(A),
+                                   _prec(precision), seed & (2 ** 64 - 1), Q.data_ptr(), _ld(Q), R.data_ptr(),
+                                   _ld(R), _stream(stream), self.info.data_ptr()), "mrcqr_execute")
+
+    def last_info(self) -> Info:
+        return read_infos(self.info)[0]
+
+    def __del__(self):
+        try:
+            if getattr(self, "_p", None) is not None and _lib is not None:
+                _lib.mrcqr_plan_destroy(self._p)
+        except Exception:
+            pass
+
+
+def factor_batched(As, precision="auto", seeds=None, stream=None):
+    """Factor a list of column-major float64 CUDA matrices; returns (Qs, Rs, infos)."""
+    k = len(As)
+    seeds = list(seeds) if seeds is not None else list(range(k))
+    precs = [precision] * k if isinstance(precision, (str, int)) else list(precision)
+    Qs = [empty_colmajor(a.shape[0], a.shape[1], a.device) for a in As]
+    Rs = [empty_colmajor(a.shape[1], a.shape[1], a.device) for a in As]
+    arr = lambda ctype, vals: (ctype * k)(*vals)
+    infos = torch.empty(INFO_BYTES * k, dtype=torch.uint8, device=As[0].device if k else "cuda")
+    code = lib().mrcqr_factor_batched(
+        k, arr(ctypes.c_void_p, [a.data_ptr() for a in As]), arr(ctypes.c_int64, [a.shape[0] for a in As]),
+        arr(ctypes.c_int64, [a.shape[1] for a in As]), arr(ctypes.c_int64, [_ld(a) for a in As]),
+        arr(ctypes.c_int32, [_prec(p) for p in precs]), arr(ctypes.c_uint64, [s & (2 ** 64 - 1) for s in seeds]),
+        arr(ctypes.c_void_p, [q.data_ptr() for q in Qs]), arr(ctypes.c_int64, [_ld(q) for q in Qs]),
+        arr(ctypes.c_void_p, [r.data_ptr() for r in Rs]), arr(ctypes.c_int64, [_ld(r) for r in Rs]),
+        _stream(stream), infos.data_ptr() if k else None)
+    _check(code, "mrcqr_factor_batched")
+    torch.cuda.synchronize()
+    return Qs, Rs, read_infos(infos, k) if k else []
+
+
+# ---- individual steps ----------------------------------------------------
+
+def draw(seed: int, m: int, s: int, signs: bool = False, device="cuda", stream=None):
+    S = torch.empty(s, dtype=torch.int32, device=device)
+    D = torch.empty(m, dtype=torch.int8, device=device) if signs else None
+    _check(lib().mrcqr_draw(seed & (2 ** 64 - 1), m, s, S.data_ptr(), D.data_ptr() if D is not None else None,
+                            _stream(stream)), "mrcqr_draw")
+    return (S, D) if signs else S
+
+
+def sketch(A: torch.Tensor, S: torch.Tensor, seed: int, precision="fp16", stream=None) -> torch.Tensor:
+    _f64_cuda(A, "A")
+    m, n = A.shape
+    s = S.shape[0]
+    Y = empty_colmajor(s, n, A.device)
+    p = _prec(precision)
+    wsb = int(lib().mrcqr_sketch_workspace_bytes(m, n, s, p))
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=A.device)
+    _check(lib().mrcqr_sketch(A.data_ptr(), m, n, _ld(A), S.data_ptr(), s, seed & (2 ** 64 - 1), p, Y.data_ptr(),
+                              _ld(Y), ws.data_ptr(), wsb, _stream(stream)), "mrcqr_sketch")
+    return Y
+
+
+def sketch_qr(Y: torch.Tensor, precision="fp32", stream=None):
+    s, n = Y.shape
+    Rs = empty_colmajor(n, n, Y.device)
+    kappa = torch.empty(1, dtype=torch.float64, device=Y.device)
+    _check(lib().mrcqr_sketch_qr(Y.data_ptr(), s, n, _ld(Y), _prec(precision), Rs.data_ptr(), _ld(Rs),
+                                 kappa.data_ptr(), _stream(stream)), "mrcqr_sketch_qr")
+    return Rs, kappa
+
+
+def trsm(A: torch.Tensor, R: torch.Tensor, X: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    m, n = A.shape
+    if X is None:
+        X = empty_colmajor(m, n, A.device)
+    _check(lib().mrcqr_trsm(A.data_ptr(), m, n, _ld(A), R.data_ptr(), _ld(R), X.data_ptr(), _ld(X),
+                            _stream(stream)), "mrcqr_trsm")
+    return X
+
+
+def gram(B: torch.Tensor, stream=None) -> torch.Tensor:
+    m, n = B.shape
+    G = empty_colmajor(n, n, B.device)
+    wsb = int(lib().mrcqr_gram_workspace_bytes(m, n))
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=B.device)
+    _check(lib().mrcqr_gram(B.data_ptr(), m, n, _ld(B), G.data_ptr(), _ld(G), ws.data_ptr(), wsb,
+                            _stream(stream)), "mrcqr_gram")
+    return G
+
+
+def cholesky(G: torch.Tensor, stream=None):
+    n = G.shape[0]
+    Rc = empty_colmajor(n, n, G.device)
+    fail = torch.empty(1, dtype=torch.int32, device=G.device)
+    kappa = torch.empty(1, dtype=torch.float64, device=G.device)
+    _check(lib().mrcqr_cholesky(G.data_ptr(), n, _ld(G), Rc.data_ptr(), _ld(Rc), fail.data_ptr(),
+                                kappa.data_ptr(), _stream(stream)), "mrcqr_cholesky")
+    return Rc, fail, kappa
+
+
+def trmm(R2: torch.Tensor, R1: torch.Tensor, stream=None) -> torch.Tensor:
+    n = R2.shape[0]
+    R = empty_colmajor(n, n, R2.device)
+    _check(lib().mrcqr_trmm(R2.data_ptr(), _ld(R2), R1.data_ptr(), _ld(R1), n, R.data_ptr(), _ld(R),
+                            _stream(stream)), "mrcqr_trmm")
+    return R
+
+
+def condest(R: torch.Tensor, stream=None) -> torch.Tensor:
+    n = R.shape[0]
+    kappa = torch.empty(1, dtype=torch.float64, device=R.device)
+    _check(lib().mrcqr_condest(R.data_ptr(), n, _ld(R), kappa.data_ptr(), _stream(stream)), "mrcqr_condest")
+    return kappa
+
+
+def version() -> int:
+    return int(lib().mrcqr_version())

@@ -1,0 +1,106 @@
+// Shared device definitions for the MRCQR gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mrcqr {
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+enum Prec : int { P_AUTO = 0, P_FP64 = 1, P_FP32 = 2, P_FP16 = 3, P_BF16 = 4 };
+
+// MFMA lane layouts on gfx950 (16x16xK, wave64), checked on the device:
+//   A operand (16 x K): lane l holds A[l % 16][(l / 16) * (K / 4) + j], j < K/4
+//   B operand (K x 16): lane l holds B[(l / 16) * (K / 4) + j][l % 16]
+//   D for the f32-accumulating 16x16x4f32 / 16x16x32 f16 / bf16 forms:
+//       lane l, register r holds D[4 * (l / 16) + r][l % 16]
+//   D for 16x16x4f64: lane l, register r holds D[4 * r + l / 16][l % 16]
+__device__ __forceinline__ int d_row_f32(int lane, int r) { return 4 * (lane >> 4) + r; }
+__device__ __forceinline__ int d_row_f64(int lane, int r) { return 4 * r + (lane >> 4); }
+
+__device__ __forceinline__ f32x4 mfma_f16(half8 a, half8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mfma_bf16(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mfma_f32(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f64x4 mfma_f64(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Counter-based generator (SplitMix64 of Steele, Lea and Flood, 2014).
+//   key(seed, stream) = mix64(seed ^ stream * 0xD1B54A32D192ED03)
+//   h(key, i)         = mix64(key + (i + 1) * 0x9E3779B97F4A7C15)
+// stream 0: Rademacher sign of row t is -1 iff bit 63 of h(key0, t) is set;
+// stream 1: Floyd sampling of S; stream 2: per-instance seeds of a batch.
+__host__ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__host__ __device__ __forceinline__ uint64_t stream_key(uint64_t seed, uint64_t stream) {
+  return mix64(seed ^ (stream * 0xD1B54A32D192ED03ull));
+}
+__host__ __device__ __forceinline__ uint64_t hash_at(uint64_t key, uint64_t i) {
+  return mix64(key + (i + 1) * 0x9E3779B97F4A7C15ull);
+}
+
+// Per-call device state (lives in the workspace).
+struct Ctrl {
+  int32_t cur_prec;     // precision of the Stage-1 attempt that is current
+  int32_t status;       // mrcqr_status so far
+  int32_t chol_fail;    // first failing Cholesky pivot or -1
+  int32_t escalations;  // AUTO escalations
+  int32_t auto_mode;    // 1 when the precision is chosen on the device
+  int32_t retry;        // 1 when the posterior check asked for a rerun
+  int32_t pad0, pad1;
+  double kappa_rs;
+  double kappa_rc;
+};
+
+// Status values (mirror of mrcqr_status in mrcqr.h).
+enum : int32_t {
+  ST_OK = 0, ST_NONFINITE = 2, ST_CHOL = 3, ST_SINGULAR = 4, ST_POSTERIOR = 7
+};
+
+// Regime bounds on the condition estimate of Rs (Section "Adaptive
+// Precision Selection": half below 1e4, single below 1e8) and the posterior
+// bound on kappa(Rc) = kappa(A Rs^{-1}): Cholesky-QR loses orthogonality
+// like kappa^2 u, so 20 keeps it near 4e-14.
+constexpr double TAU_FP16 = 1e4;
+constexpr double TAU_FP32 = 1e8;
+constexpr double TAU_BF16 = 1e2;
+constexpr double TAU_POSTERIOR = 20.0;
+
+// Launch gating of the static launch sequence (no host round trip):
+//   phase 0: first pass, always runs;
+//   phase 1: rerun pass, runs only when the posterior check asked for it;
+//   phase 2: tail of the first pass (Q and R), skipped when a rerun follows.
+// A Stage-1 kernel for precision slot_prec runs only while that precision
+// is the current one (P_AUTO = any).
+enum Phase : int { PH_FIRST = 0, PH_RERUN = 1, PH_FIRST_TAIL = 2 };
+
+__device__ __forceinline__ bool skip_launch(const Ctrl* ctrl, int slot_prec, int phase) {
+  if (ctrl == nullptr) return false;
+  if (phase == PH_RERUN && !ctrl->retry) return true;
+  if (phase == PH_FIRST_TAIL && ctrl->retry) return true;
+  return slot_prec != P_AUTO && ctrl->cur_prec != slot_prec;
+}
+
+// Raise a kernel's dynamic LDS limit to `bytes` when above the default
+// 64 KiB; the call's own error state is cleared so that a later
+// hipGetLastError() reports only launch failures.
+inline void allow_dynamic_lds(const void* fn, size_t bytes) {
+  if (bytes > 65536) {
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    (void)hipGetLastError();
+  }
+}
+
+}  // namespace mrcqr

@@ -1,0 +1,101 @@
+// Algorithm 2, Stage 1, first step: draw the row sample S and the signs D.
+//
+// S is Floyd's uniform s-subset of [0, m): for j = m-s .. m-1 take
+// r_j = floor(h(key1, j) * (j + 1) / 2^64) in [0, j]; insert r_j unless it is
+// already present, else insert j. If all r_j are distinct no insertion ever
+// collides and S = {r_j}; that case is detected after sorting (no two equal
+// neighbours) and needs no sequential pass. Otherwise one wave replays the
+// insertions in order, keeping the set in registers (membership by ballot).
+#include "common.hpp"
+
+namespace mrcqr {
+
+constexpr int DRAW_THREADS = 1024;
+constexpr int DRAW_SMAX = 2048;           // largest supported s
+constexpr int DRAW_SLOTS = DRAW_SMAX / 64;
+
+__device__ __forceinline__ uint32_t floyd_r(uint64_t key1, uint64_t j) {
+  return (uint32_t)__umul64hi(hash_at(key1, j), j + 1);
+}
+
+__device__ void bitonic_sort(uint32_t* keys, int P) {
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < P; i += blockDim.x) {
+        int ixj = i ^ j;
+        if (ixj > i) {
+          uint32_t a = keys[i], b = keys[ixj];
+          bool up = (i & k) == 0;
+          if ((a > b) == up) { keys[i] = b; keys[ixj] = a; }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__global__ __launch_bounds__(DRAW_THREADS) void draw_kernel(uint64_t seed, int m, int s, int32_t* S_out) {
+  __shared__ uint32_t keys[DRAW_SMAX];
+  __shared__ int dup;
+  const uint64_t key1 = stream_key(seed, 1);
+  int P = 1;
+  while (P < s) P <<= 1;
+  for (int i = threadIdx.x; i < P; i += blockDim.x)
+    keys[i] = (i < s) ? floyd_r(key1, (uint64_t)(m - s + i)) : 0xFFFFFFFFu;
+  if (threadIdx.x == 0) dup = 0;
+  __syncthreads();
+  bitonic_sort(keys, P);
+  for (int i = threadIdx.x; i + 1 < s; i += blockDim.x)
+    if (keys[i] == keys[i + 1]) dup = 1;
+  __syncthreads();
+  if (dup) {
+    // Sequential replay of Floyd's insertions by wave 0.
+    if (threadIdx.x < 64) {
+      const int lane = threadIdx.x;
+      uint32_t slot[DRAW_SLOTS];
+#pragma unroll
+      for (int q = 0; q < DRAW_SLOTS; ++q) slot[q] = 0xFFFFFFFFu;
+      for (int it = 0; it < s; ++it) {
+        const uint32_t j = (uint32_t)(m - s + it);
+        const uint32_t r = floyd_r(key1, j);
+        bool hit = false;
+#pragma unroll
+        for (int q = 0; q < DRAW_SLOTS; ++q) hit |= (slot[q] == r);
+        const bool found = __any(hit);
+        const uint32_t v = found ? j : r;
+        if (lane == (it & 63)) {
+          const int qq = it >> 6;
+#pragma unroll
+          for (int q = 0; q < DRAW_SLOTS; ++q)
+            if (q == qq) slot[q] = v;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < DRAW_SLOTS; ++q) {
+        const int idx = lane + 64 * q;
+        if (idx < P) keys[idx] = (idx < s) ? slot[q] : 0xFFFFFFFFu;
+      }
+    }
+    __syncthreads();
+    bitonic_sort(keys, P);
+  }
+  for (int i = threadIdx.x; i < s; i += blockDim.x) S_out[i] = (int32_t)keys[i];
+}
+
+__global__ void signs_kernel(uint64_t seed, int m, int8_t* D) {
+  const uint64_t key0 = stream_key(seed, 0);
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < m; t += gridDim.x * blockDim.x)
+    D[t] = (hash_at(key0, (uint64_t)t) >> 63) ? (int8_t)-1 : (int8_t)1;
+}
+
+hipError_t launch_draw(uint64_t seed, int m, int s, int32_t* S, int8_t* D, hipStream_t st) {
+  hipLaunchKernelGGL(draw_kernel, dim3(1), dim3(DRAW_THREADS), 0, st, seed, m, s, S);
+  if (D) {
+    int blocks = (m + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(signs_kernel, dim3(blocks), dim3(256), 0, st, seed, m, D);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace mrcqr

@@ -1,0 +1,119 @@
+// Algorithm 1, first step, in float64: the Gram matrix G = B^T B of the
+// preconditioned m x n matrix. Only the upper 16 x 16 tiles are formed
+// (symmetric rank-k update). Grid = row chunks; a workgroup of 4 waves
+// stages 64-row panels of B in LDS (row-major, coalesced column loads) and
+// each wave accumulates its share of the upper tiles with float64 MFMA
+// 16x16x4. Per-chunk partials are summed in a second kernel in fixed order
+// (deterministic, no atomics).
+#include "common.hpp"
+
+namespace mrcqr {
+
+constexpr int GR_THREADS = 256;
+constexpr int GR_PANEL = 64;
+constexpr int GR_NMAX = 128;
+constexpr int GR_LDT = GR_NMAX + 1;
+constexpr int GR_TPW = 9;  // tiles per wave: 36 upper tiles for n = 128 over 4 waves
+
+__global__ __launch_bounds__(GR_THREADS) void syrk_kernel(
+    const double* __restrict__ B, int m, int n, int64_t ldb, int rows_per_chunk,
+    double* __restrict__ Gpart, const Ctrl* __restrict__ ctrl, int phase) {
+  __shared__ double tile[GR_PANEL * GR_LDT];
+  if (skip_launch(ctrl, P_AUTO, phase)) return;
+  const int tid = threadIdx.x;
+  const int w = tid >> 6, l = tid & 63, g = l >> 4, c16 = l & 15;
+  const int nb = (n + 15) / 16;
+  const int ntiles = nb * (nb + 1) / 2;
+  const int ncols = 16 * nb;
+  const int64_t tstart = (int64_t)blockIdx.x * rows_per_chunk;
+  const int64_t tend = min((int64_t)m, tstart + rows_per_chunk);
+
+  int tI[GR_TPW], tJ[GR_TPW];
+#pragma unroll
+  for (int q = 0; q < GR_TPW; ++q) {
+    int tt = w + 4 * q, I = 0;
+    if (tt >= ntiles) { tI[q] = -1; tJ[q] = -1; continue; }
+    // upper tiles in row order: (0,0),(0,1),...,(0,nb-1),(1,1),...
+    while (tt >= nb - I) { tt -= nb - I; ++I; }
+    tI[q] = I; tJ[q] = I + tt;
+  }
+  f64x4 acc[GR_TPW];
+#pragma unroll
+  for (int q = 0; q < GR_TPW; ++q) acc[q] = f64x4{0, 0, 0, 0};
+
+  for (int64_t t0 = tstart; t0 < tend; t0 += GR_PANEL) {
+    __syncthreads();
+    for (int e = tid; e < GR_PANEL * ncols; e += GR_THREADS) {
+      const int col = e / GR_PANEL, row = e % GR_PANEL;
+      const int64_t t = t0 + row;
+      tile[row * GR_LDT + col] = (t < tend && col < n) ? B[t + (int64_t)col * ldb] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < GR_PANEL / 4; ++kk) {
+      const double* trow = &tile[(4 * kk + g) * GR_LDT + c16];
+#pragma unroll
+      for (int q = 0; q < GR_TPW; ++q) {
+        if (tI[q] < 0) break;
+        const double a = trow[16 * tI[q]];
+        const double b = trow[16 * tJ[q]];
+        acc[q] = mfma_f64(a, b, acc[q]);
+      }
+    }
+  }
+  // Gpart[chunk][col][row] for the upper tiles (f64 D layout)
+  double* Gp = Gpart + (int64_t)blockIdx.x * n * n;
+#pragma unroll
+  for (int q = 0; q < GR_TPW; ++q) {
+    if (tI[q] < 0) break;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * tI[q] + d_row_f64(l, r);
+      const int col = 16 * tJ[q] + c16;
+      if (row < n && col < n) Gp[(int64_t)col * n + row] = acc[q][r];
+    }
+  }
+}
+
+// G[i, j] = G[j, i] = sum over chunks (fixed order) of the upper partial (i <= j).
+__global__ void gram_reduce_kernel(const double* __restrict__ Gpart, int chunks, int n,
+                                   double* __restrict__ G, int64_t ldg, const Ctrl* __restrict__ ctrl, int phase) {
+  if (skip_launch(ctrl, P_AUTO, phase)) return;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * n) return;
+  const int i = idx % n, j = idx / n;
+  if (i > j) return;
+  double acc = 0.0;
+  for (int k = 0; k < chunks; ++k) acc += Gpart[(int64_t)k * n * n + (int64_t)j * n + i];
+  G[i + (int64_t)j * ldg] = acc;
+  G[j + (int64_t)i * ldg] = acc;
+}
+
+struct GramGeom { int chunks, rows_per_chunk; };
+
+GramGeom gram_geometry(int64_t m) {
+  const int64_t npan = (m + GR_PANEL - 1) / GR_PANEL;
+  const int64_t target = 512;
+  const int64_t per = (npan + target - 1) / target;
+  GramGeom gg;
+  gg.rows_per_chunk = (int)(per * GR_PANEL);
+  gg.chunks = (int)((m + gg.rows_per_chunk - 1) / gg.rows_per_chunk);
+  return gg;
+}
+
+size_t gram_partial_bytes(int64_t m, int64_t n) {
+  GramGeom gg = gram_geometry(m);
+  return (size_t)gg.chunks * (size_t)n * (size_t)n * sizeof(double);
+}
+
+hipError_t launch_gram(const double* B, int m, int n, int64_t ldb, double* Gpart, double* G, int64_t ldg,
+                       const Ctrl* ctrl, int phase, hipStream_t st) {
+  if (n > GR_NMAX) return hipErrorInvalidValue;
+  GramGeom gg = gram_geometry(m);
+  hipLaunchKernelGGL(syrk_kernel, dim3(gg.chunks), dim3(GR_THREADS), 0, st, B, m, n, ldb, gg.rows_per_chunk, Gpart, ctrl, phase);
+  const int tot = n * n;
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3((tot + 255) / 256), dim3(256), 0, st, (const double*)Gpart, gg.chunks, n, G, ldg, ctrl, phase);
+  return hipGetLastError();
+}
+
+}  // namespace mrcqr

@@ -1,0 +1,377 @@
+// Algorithm 2, Stage 1: DiagMult (sign flip + cast to p), the DCT-II
+// transform along the rows, and Select (the s sampled rows), computed as one
+// dense contraction Y = C_S * fl_p(D A) on the matrix cores, where
+// C_S[i, t] = cos(pi (2t+1) S[i] / (2m)) are generated on the fly.
+//
+// Work decomposition: grid (row chunks, column blocks of 128, sketch-row
+// blocks of 256). A workgroup of 8 waves streams its row chunk in panels of
+// 64 rows: the panel is loaded once (coalesced, 512 B per column), signed,
+// block-prescaled and cast, and written to LDS in the layout of the MFMA B
+// operand; each wave generates the coefficients of its 32 sketch rows
+// straight into A-operand registers and multiplies against the whole panel.
+// Partial sums per row chunk are reduced in a second kernel in fixed order.
+//
+// Coefficients: the phase (2t+1)k mod 4m is tracked in exact integer
+// arithmetic; FP32/FP64 sketches evaluate every coefficient from its phase
+// (quadrant reduction + Taylor polynomials on [0, pi/4]); FP16/BF16 evaluate
+// one coefficient per run of 8 consecutive rows and rotate by the angle of
+// one row step (7 rotations, error ~1e-6, far below the 2^-11 / 2^-8 unit
+// roundoff of the target format).
+#include "common.hpp"
+
+namespace mrcqr {
+
+constexpr int SK_THREADS = 512;
+constexpr int SK_SBLK = 256;
+constexpr int SK_NBLK = 128;
+constexpr int SK_PANEL = 64;
+
+template <int P> struct SkT;
+template <> struct SkT<P_FP16> { using elem = _Float16; using acc = float; static constexpr int KSTEP = 32; static constexpr int LD = 72; };
+template <> struct SkT<P_BF16> { using elem = __bf16;   using acc = float; static constexpr int KSTEP = 32; static constexpr int LD = 72; };
+template <> struct SkT<P_FP32> { using elem = float;    using acc = float; static constexpr int KSTEP = 4;  static constexpr int LD = 66; };
+template <> struct SkT<P_FP64> { using elem = double;   using acc = double; static constexpr int KSTEP = 4; static constexpr int LD = 66; };
+
+// ---- cos/sin of the DCT-II phase --------------------------------------
+// angle = (pi/2) * phi / m for an integer phase phi in [0, 4m).
+// Taylor series of cos and sin on [0, pi/4] (truncation below 1.2e-10 in
+// float, below 4e-21 in double).
+__device__ __forceinline__ void taylor_f32(float th, float& c, float& s) {
+  const float t2 = th * th;
+  c = 1.0f + t2 * (-1.0f / 2 + t2 * (1.0f / 24 + t2 * (-1.0f / 720 + t2 * (1.0f / 40320 + t2 * (-1.0f / 3628800)))));
+  s = th * (1.0f + t2 * (-1.0f / 6 + t2 * (1.0f / 120 + t2 * (-1.0f / 5040 + t2 * (1.0f / 362880 + t2 * (-1.0f / 39916800))))));
+}
+__device__ __forceinline__ void taylor_f64(double th, double& c, double& s) {
+  const double t2 = th * th;
+  c = 1.0 + t2 * (-1.0 / 2 + t2 * (1.0 / 24 + t2 * (-1.0 / 720 + t2 * (1.0 / 40320 + t2 * (-1.0 / 3628800
+      + t2 * (1.0 / 479001600.0 + t2 * (-1.0 / 87178291200.0 + t2 * (1.0 / 20922789888000.0
+      + t2 * (-1.0 / 6402373705728000.0)))))))));
+  s = th * (1.0 + t2 * (-1.0 / 6 + t2 * (1.0 / 120 + t2 * (-1.0 / 5040 + t2 * (1.0 / 362880 + t2 * (-1.0 / 39916800.0
+      + t2 * (1.0 / 6227020800.0 + t2 * (-1.0 / 1307674368000.0 + t2 * (1.0 / 355687428096000.0
+      + t2 * (-1.0 / 121645100408832000.0))))))))));
+}
+
+template <typename F>
+__device__ __forceinline__ void phase_sincos(uint32_t phi, uint32_t m, F inv_m, F& cs, F& sn) {
+  const uint32_t q = (uint32_t)(phi >= m) + (uint32_t)(phi >= 2u * m) + (uint32_t)(phi >= 3u * m);
+  const uint32_t r = phi - q * m;
+  const bool swap = 2u * r > m;
+  const uint32_t rr = swap ? m - r : r;
+  const F th = (F)rr * inv_m * (F)1.5707963267948966192;
+  F c0, s0;
+  if constexpr (sizeof(F) == 4) taylor_f32(th, c0, s0); else taylor_f64(th, c0, s0);
+  const F ca = swap ? s0 : c0;  // cos and sin of the angle inside the quadrant
+  const F sa = swap ? c0 : s0;
+  cs = (q == 0) ? ca : (q == 1) ? -sa : (q == 2) ? -ca : sa;
+  sn = (q == 0) ? sa : (q == 1) ? ca : (q == 2) ? -sa : -ca;
+}
+
+__device__ __forceinline__ uint32_t phase_of(uint64_t t, uint64_t k, uint64_t m4) {
+  return (uint32_t)(((2 * t + 1) * k) % m4);
+}
+__device__ __forceinline__ uint32_t add_mod(uint32_t a, uint32_t b, uint32_t m4) {
+  uint32_t c = a + b;
+  return c >= m4 ? c - m4 : c;
+}
+
+// Block power-of-two exponent: mu * 2^e in [2^14, 2^15), clamped to
+// [-100, 100]; 0 when mu is 0 or not finite.
+__device__ __forceinline__ int block_exp(double mu) {
+  if (!(mu > 0.0) || !isfinite(mu)) return 0;
+  int E;
+  (void)frexp(mu, &E);
+  int e = 15 - E;
+  return e < -100 ? -100 : (e > 100 ? 100 : e);
+}
+
+template <int P>
+__global__ __launch_bounds__(SK_THREADS) void sketch_kernel(
+    const double* __restrict__ A, int64_t lda, int m, int n,
+    const int32_t* __restrict__ S, int s, uint64_t seed, int rows_per_chunk,
+    typename SkT<P>::acc* __restrict__ Ypart, const Ctrl* __restrict__ ctrl, int phase) {
+  using T = SkT<P>;
+  using elem = typename T::elem;
+  using acc_t = typename T::acc;
+  constexpr int KSTEP = T::KSTEP;
+  constexpr int LD = T::LD;
+  constexpr int NKS = SK_PANEL / KSTEP;
+  constexpr bool LOWP = (P != P_FP64);
+
+  if (skip_launch(ctrl, P, phase)) return;
+
+  __shared__ __attribute__((aligned(16))) elem tile[2][SK_NBLK * LD];
+  __shared__ float esc[2][SK_NBLK];
+  __shared__ int sgn[2][SK_PANEL];
+
+  const int tid = threadIdx.x;
+  const int w = tid >> 6, l = tid & 63, g = l >> 4, c16 = l & 15;
+  const int chunk = blockIdx.x;
+  const int cbase = blockIdx.y * SK_NBLK;
+  const int sbase = blockIdx.z * SK_SBLK + w * 32;
+  const int64_t tstart = (int64_t)chunk * rows_per_chunk;
+  const int64_t tend = min((int64_t)m, tstart + rows_per_chunk);
+  const int npanels = (int)((tend - tstart + SK_PANEL - 1) / SK_PANEL);
+  const uint32_t um = (uint32_t)m, m4 = 4u * (uint32_t)m;
+  const uint64_t key0 = stream_key(seed, 0);
+
+  // ---- this lane's two sketch rows (one per M tile) and their phases ----
+  uint32_t kk[2], phi[2], inc_k[2], inc_p[2];
+  bool kvalid[2];
+  float cd[2], sd[2];
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt) {
+    const int row = sbase + 16 * mt + c16;
+    kvalid[mt] = row < s;
+    const uint32_t k = kvalid[mt] ? (uint32_t)S[row] : 0u;
+    kk[mt] = k;
+    // lane's first row in a panel: t0 + 8g (K=32 forms) or t0 + g (K=4 forms)
+    const uint64_t tl = (uint64_t)tstart + (KSTEP == 32 ? 8 * g : g);
+    phi[mt] = phase_of(tl, k, m4);
+    inc_k[mt] = (uint32_t)((2ull * KSTEP * k) % m4);        // one K step
+    inc_p[mt] = (uint32_t)((2ull * SK_PANEL * k) % m4);     // one panel
+    if constexpr (KSTEP == 32) {
+      float c, sn;
+      phase_sincos<float>((uint32_t)((2ull * k) % m4), um, 1.0f / (float)m, c, sn);
+      cd[mt] = c; sd[mt] = sn;
+    }
+  }
+  const float inv_mf = 1.0f / (float)m;
+  const double inv_md = 1.0 / (double)m;
+
+  // ---- accumulators ----
+  typedef typename std::conditional<LOWP, f32x4, f64x4>::type accv;
+  accv acc[2][8];
+  accv accp[2][8];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) { acc[a][b] = accv{0, 0, 0, 0}; accp[a][b] = accv{0, 0, 0, 0}; }
+
+  // ---- panel loader: thread covers columns cl_r = w*16 + r*8 + l/8 (r = 0,1),
+  //      rows 8*(l%8) .. +7 of the panel ----
+  double regs[16];
+  const int lrow = 8 * (l & 7);
+  auto load_panel = [&](int64_t t0) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int col = cbase + w * 16 + r * 8 + (l >> 3);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int64_t t = t0 + lrow + i;
+        regs[r * 8 + i] = (col < n && t < tend) ? A[t + (int64_t)col * lda] : 0.0;
+      }
+    }
+  };
+  auto signs_for = [&](int64_t t0, int buf) {
+    if (w == 0) {
+      const int64_t t = t0 + l;
+      sgn[buf][l] = (t < tend) ? (int)(hash_at(key0, (uint64_t)t) >> 63) : 0;
+    }
+  };
+
+  if (npanels > 0) {
+    load_panel(tstart);
+    signs_for(tstart, 0);
+  }
+  __syncthreads();
+
+  for (int p = 0; p < npanels; ++p) {
+    const int buf = p & 1;
+    const int64_t t0 = tstart + (int64_t)p * SK_PANEL;
+    // 1. sign, prescale, cast, store to LDS
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int cl = w * 16 + r * 8 + (l >> 3);
+      int e = 0;
+      if constexpr (LOWP) {
+        double mx = 0.0;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) mx = fmax(mx, fabs(regs[r * 8 + i]));
+        // propagate a NaN so the whole block keeps it (fmax drops NaN)
+        bool bad = false;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) bad |= !isfinite(regs[r * 8 + i]);
+        mx = bad ? __builtin_inf() : mx;
+        mx = fmax(mx, __shfl_xor(mx, 1));
+        mx = fmax(mx, __shfl_xor(mx, 2));
+        mx = fmax(mx, __shfl_xor(mx, 4));
+        e = block_exp(mx);
+        if ((l & 7) == 0) esc[buf][cl] = ldexpf(1.0f, -e);
+      }
+      elem* dst = &tile[buf][cl * LD + lrow];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        double v = regs[r * 8 + i];
+        if (sgn[buf][lrow + i]) v = -v;
+        if constexpr (LOWP) {
+          const float f = (float)ldexp(v, e);
+          dst[i] = (elem)f;
+        } else {
+          dst[i] = v;
+        }
+      }
+    }
+    // 2. prefetch the next panel
+    if (p + 1 < npanels) {
+      load_panel(t0 + SK_PANEL);
+      signs_for(t0 + SK_PANEL, buf ^ 1);
+    }
+    __syncthreads();
+
+    // 3. contraction of this panel
+    const elem* tb = tile[buf];
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) {
+      if constexpr (KSTEP == 32) {
+        typedef typename std::conditional<P == P_FP16, half8, bf16x8>::type vec8;
+        vec8 bop[8];
+#pragma unroll
+        for (int nt = 0; nt < 8; ++nt)
+          bop[nt] = *reinterpret_cast<const vec8*>(&tb[(16 * nt + c16) * LD + KSTEP * ks + 8 * g]);
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+          float c, sn;
+          phase_sincos<float>(phi[mt], um, inv_mf, c, sn);
+          vec8 aop;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            aop[j] = kvalid[mt] ? (typename SkT<P>::elem)c : (typename SkT<P>::elem)0.0f;
+            const float cn = c * cd[mt] - sn * sd[mt];
+            const float snn = sn * cd[mt] + c * sd[mt];
+            c = cn; sn = snn;
+          }
+#pragma unroll
+          for (int nt = 0; nt < 8; ++nt) {
+            if constexpr (P == P_FP16) accp[mt][nt] = mfma_f16(aop, bop[nt], accp[mt][nt]);
+            else accp[mt][nt] = mfma_bf16(aop, bop[nt], accp[mt][nt]);
+          }
+          phi[mt] = add_mod(phi[mt], inc_k[mt], m4);
+        }
+      } else {
+        elem bop[8];
+#pragma unroll
+        for (int nt = 0; nt < 8; ++nt) bop[nt] = tb[(16 * nt + c16) * LD + KSTEP * ks + g];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+          elem a;
+          if constexpr (P == P_FP32) {
+            float c, sn;
+            phase_sincos<float>(phi[mt], um, inv_mf, c, sn);
+            a = kvalid[mt] ? c : 0.0f;
+          } else {
+            double c, sn;
+            phase_sincos<double>(phi[mt], um, inv_md, c, sn);
+            a = kvalid[mt] ? c : 0.0;
+          }
+#pragma unroll
+          for (int nt = 0; nt < 8; ++nt) {
+            if constexpr (P == P_FP32) accp[mt][nt] = mfma_f32(a, bop[nt], accp[mt][nt]);
+            else acc[mt][nt] = mfma_f64(a, bop[nt], acc[mt][nt]);
+          }
+          phi[mt] = add_mod(phi[mt], inc_k[mt], m4);
+        }
+      }
+    }
+    // phases: NKS steps of inc_k advanced one panel minus nothing; the panel
+    // step equals NKS * inc_k (mod 4m), so phi is already at the next panel.
+    (void)inc_p;
+    if constexpr (LOWP) {
+      // undo the block prescale of this panel (one power of two per column)
+#pragma unroll
+      for (int nt = 0; nt < 8; ++nt) {
+        const float sc = esc[buf][16 * nt + c16];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[mt][nt][r] = fmaf(accp[mt][nt][r], sc, acc[mt][nt][r]);
+          accp[mt][nt] = accv{0, 0, 0, 0};
+        }
+      }
+    }
+  }
+
+  // ---- partial sums of this row chunk: Ypart[(chunk*n + col)*s + srow] ----
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < 8; ++nt) {
+      const int col = cbase + 16 * nt + c16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int srow = sbase + 16 * mt + (LOWP ? d_row_f32(l, r) : d_row_f64(l, r));
+        if (col < n && srow < s)
+          Ypart[((int64_t)chunk * n + col) * s + srow] = acc[mt][nt][r];
+      }
+    }
+}
+
+// Y[srow, col] = gamma_k * sum over chunks (fixed order, float64), then
+// rounded to float32 for the low-precision sketches.
+template <typename AccT>
+__global__ void sketch_reduce_kernel(const AccT* __restrict__ Ypart, int chunks, int n, int s,
+                                     const int32_t* __restrict__ S, double* __restrict__ Y, int64_t ldy,
+                                     int round_f32, const Ctrl* __restrict__ ctrl, int slot, int phase) {
+  if (skip_launch(ctrl, slot, phase)) return;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n * s) return;
+  const int col = (int)(idx / s), srow = (int)(idx % s);
+  double acc = 0.0;
+  for (int c = 0; c < chunks; ++c) acc += (double)Ypart[((int64_t)c * n + col) * s + srow];
+  const double gamma = (S[srow] == 0) ? sqrt(1.0 / (double)s) : sqrt(2.0 / (double)s);
+  double y = gamma * acc;
+  if (round_f32) y = (double)(float)y;
+  Y[srow + (int64_t)col * ldy] = y;
+}
+
+// ---- host-side launch -------------------------------------------------
+struct SketchGeom { int chunks, rows_per_chunk; };
+
+SketchGeom sketch_geometry(int64_t m) {
+  const int64_t npan = (m + SK_PANEL - 1) / SK_PANEL;
+  const int64_t target = 256;
+  const int64_t per = (npan + target - 1) / target;
+  SketchGeom gg;
+  gg.rows_per_chunk = (int)(per * SK_PANEL);
+  gg.chunks = (int)((m + gg.rows_per_chunk - 1) / gg.rows_per_chunk);
+  return gg;
+}
+
+size_t sketch_partial_bytes(int64_t m, int64_t n, int64_t s, int prec) {
+  SketchGeom gg = sketch_geometry(m);
+  const size_t el = (prec == P_FP64) ? sizeof(double) : sizeof(float);
+  return (size_t)gg.chunks * (size_t)n * (size_t)s * el;
+}
+
+hipError_t launch_sketch(int prec, const double* A, int64_t lda, int m, int n, const int32_t* S, int s,
+                         uint64_t seed, void* Ypart, double* Y, int64_t ldy, const Ctrl* ctrl, int phase,
+                         hipStream_t st) {
+  SketchGeom gg = sketch_geometry(m);
+  dim3 grid(gg.chunks, (n + SK_NBLK - 1) / SK_NBLK, (s + SK_SBLK - 1) / SK_SBLK);
+  dim3 block(SK_THREADS);
+  const int rb = 256;
+  const int64_t tot = (int64_t)n * s;
+  dim3 rgrid((unsigned)((tot + rb - 1) / rb));
+  switch (prec) {
+    case P_FP16:
+      hipLaunchKernelGGL(sketch_kernel<P_FP16>, grid, block, 0, st, A, lda, m, n, S, s, seed, gg.rows_per_chunk, (float*)Ypart, ctrl, phase);
+      hipLaunchKernelGGL(sketch_reduce_kernel<float>, rgrid, dim3(rb), 0, st, (const float*)Ypart, gg.chunks, n, s, S, Y, ldy, 1, ctrl, (int)P_FP16, phase);
+      break;
+    case P_BF16:
+      hipLaunchKernelGGL(sketch_kernel<P_BF16>, grid, block, 0, st, A, lda, m, n, S, s, seed, gg.rows_per_chunk, (float*)Ypart, ctrl, phase);
+      hipLaunchKernelGGL(sketch_reduce_kernel<float>, rgrid, dim3(rb), 0, st, (const float*)Ypart, gg.chunks, n, s, S, Y, ldy, 1, ctrl, (int)P_BF16, phase);
+      break;
+    case P_FP32:
+      hipLaunchKernelGGL(sketch_kernel<P_FP32>, grid, block, 0, st, A, lda, m, n, S, s, seed, gg.rows_per_chunk, (float*)Ypart, ctrl, phase);
+      hipLaunchKernelGGL(sketch_reduce_kernel<float>, rgrid, dim3(rb), 0, st, (const float*)Ypart, gg.chunks, n, s, S, Y, ldy, 1, ctrl, (int)P_FP32, phase);
+      break;
+    case P_FP64:
+      hipLaunchKernelGGL(sketch_kernel<P_FP64>, grid, block, 0, st, A, lda, m, n, S, s, seed, gg.rows_per_chunk, (double*)Ypart, ctrl, phase);
+      hipLaunchKernelGGL(sketch_reduce_kernel<double>, rgrid, dim3(rb), 0, st, (const double*)Ypart, gg.chunks, n, s, S, Y, ldy, 0, ctrl, (int)P_FP64, phase);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace mrcqr

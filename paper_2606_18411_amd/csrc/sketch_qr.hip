@@ -1,0 +1,247 @@
+// Algorithm 2, Stage 1, SketchQR and the promotion of Rs to float64, plus
+// the condition estimate that drives the adaptive precision choice
+// (Section "Adaptive Precision Selection").
+//
+// Householder thin QR of the s x n sketch Y in one workgroup of 1024
+// threads. Y lives in registers: thread t owns column t / TPC and rows
+// (t % TPC) + TPC * i, i < RB (TPC threads per column sit in one wave, so
+// column reductions are wave shuffles). Step j: the owner group of column j
+// forms the reflector (LAPACK larfg convention: beta = -sign(alpha) ||x||,
+// tau = (beta - alpha) / beta, v = x / (alpha - beta), v_j = 1), publishes v
+// and tau in LDS (double-buffered, one barrier per step), and every column
+// c > j applies H = I - tau v v^T. Arithmetic is float32 for FP16/BF16/FP32
+// sketches and float64 for FP64 sketches. Rs gets diag >= 0 by flipping
+// rows and is widened to float64.
+//
+// The ICE estimate (Bischof 1990) of kappa_2 runs in wave 0 afterwards.
+#include "common.hpp"
+#include "ice.hpp"
+
+namespace mrcqr {
+
+constexpr int QR_THREADS = 1024;
+
+template <typename T>
+__device__ __forceinline__ T group_sum(T v, int tpc) {
+  for (int o = tpc >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+template <typename T, int RB, int NT>
+__global__ __launch_bounds__(NT) void householder_kernel(
+    const double* __restrict__ Y, int s, int n, int64_t ldy, int tpc,
+    double* __restrict__ Rs, int64_t ldr, double* __restrict__ kappa_out,
+    Ctrl* __restrict__ ctrl, int slot, int phase) {
+  if (skip_launch(ctrl, slot, phase)) return;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  double* Rl = reinterpret_cast<double*>(smem);          // n * n, column-major
+  T* vbuf = reinterpret_cast<T*>(Rl + (size_t)n * n);    // 2 * s
+  T* taus = vbuf + 2 * s;                                // 2
+  float* dsign = reinterpret_cast<float*>(taus + 2);     // n
+  __shared__ int bad_flag;
+
+  const int tid = threadIdx.x;
+  const int c = tid / tpc, rb = tid % tpc;
+  const bool active = c < n;
+  T y[RB];
+#pragma unroll
+  for (int i = 0; i < RB; ++i) {
+    const int r = rb + tpc * i;
+    y[i] = (active && r < s) ? (T)Y[r + (int64_t)c * ldy] : (T)0;
+  }
+  if (tid == 0) bad_flag = 0;
+
+  // Exact power-of-two prescale so that squares stay in range: Y * 2^es has
+  // max magnitude in [0.5, 1); R is scaled back by 2^-es at the end.
+  __shared__ double wmax[NT / 64];
+  {
+    double lm = 0.0;
+#pragma unroll
+    for (int i = 0; i < RB; ++i) lm = fmax(lm, fabs((double)y[i]));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) lm = fmax(lm, __shfl_xor(lm, o));
+    if ((tid & 63) == 0) wmax[tid >> 6] = lm;
+  }
+  __syncthreads();
+  int es = 0;
+  {
+    double gm = 0.0;
+    for (int w = 0; w < NT / 64; ++w) gm = fmax(gm, wmax[w]);
+    if (gm > 0.0 && isfinite(gm)) { int E; (void)frexp(gm, &E); es = -E; }
+  }
+#pragma unroll
+  for (int i = 0; i < RB; ++i) y[i] = (T)ldexp((double)y[i], es);
+
+  for (int j = 0; j < n; ++j) {
+    const int buf = j & 1;
+    T* v = vbuf + buf * s;
+    if (c == j) {
+      const int rb0 = j % tpc, i0 = j / tpc;
+      T alpha_l = (T)0, sp[4] = {(T)0, (T)0, (T)0, (T)0};
+#pragma unroll
+      for (int i = 0; i < RB; ++i) {
+        const int r = rb + tpc * i;
+        if (r == j) alpha_l = y[i];
+        if (r > j && r < s) sp[i & 3] += y[i] * y[i];
+      }
+      T sig = (sp[0] + sp[1]) + (sp[2] + sp[3]);
+      const T alpha = group_sum(alpha_l, tpc);  // only lane rb0 contributes
+      sig = group_sum(sig, tpc);
+      T tau, beta, scal;
+      if (sig == (T)0) { tau = (T)0; beta = alpha; scal = (T)0; }
+      else {
+        const T nrm = sqrt(alpha * alpha + sig);
+        beta = signbit(alpha) ? nrm : -nrm;
+        tau = (beta - alpha) / beta;
+        scal = (T)1 / (alpha - beta);
+      }
+#pragma unroll
+      for (int i = 0; i < RB; ++i) {
+        const int r = rb + tpc * i;
+        if (r < s) v[r] = (r > j) ? y[i] * scal : (r == j ? (T)1 : (T)0);
+        if (r == j) y[i] = beta;
+      }
+      if (rb == rb0) taus[buf] = tau;
+      (void)i0;
+    }
+    __syncthreads();
+    if (active && c > j) {
+      const T tau = taus[buf];
+      if (tau != (T)0) {
+        T dp[4] = {(T)0, (T)0, (T)0, (T)0};
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+          const int r = rb + tpc * i;
+          if (r >= j && r < s) dp[i & 3] += v[r] * y[i];
+        }
+        T d = (dp[0] + dp[1]) + (dp[2] + dp[3]);
+        d = group_sum(d, tpc);
+        const T f = tau * d;
+#pragma unroll
+        for (int i = 0; i < RB; ++i) {
+          const int r = rb + tpc * i;
+          if (r >= j && r < s) y[i] -= f * v[r];
+        }
+      }
+    }
+  }
+
+  // diag(R) >= 0: flip rows with a negative pivot; widen to float64.
+  if (active) {
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+      const int r = rb + tpc * i;
+      if (r == c) dsign[c] = (y[i] < (T)0) ? -1.0f : 1.0f;
+    }
+  }
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+      const int r = rb + tpc * i;
+      if (r < n) {
+        const double val = (r <= c) ? ldexp((double)y[i] * (double)dsign[r], -es) : 0.0;
+        Rs[r + (int64_t)c * ldr] = val;
+        Rl[r + c * n] = val;
+        if (r == c && !(val > 0.0 && isfinite(val))) bad_flag = 1;
+        if (r < c && !isfinite(val)) bad_flag = 1;
+      }
+    }
+  }
+  __syncthreads();
+  if (tid < 64) {
+    double kappa = bad_flag ? __builtin_inf() : ice_kappa(Rl, n, 1, n);
+    if (tid == 0) {
+      if (kappa_out) *kappa_out = kappa;
+      if (ctrl) {
+        ctrl->kappa_rs = kappa;
+        const int p = ctrl->cur_prec;
+        const bool can_escalate = ctrl->auto_mode && (p == P_FP16 || p == P_FP32);
+        const double tau_p = (p == P_FP16) ? TAU_FP16 : (p == P_FP32 ? TAU_FP32 : (p == P_BF16 ? TAU_BF16 : __builtin_inf()));
+        if (bad_flag) {
+          if (can_escalate) { ctrl->cur_prec = (p == P_FP16) ? P_FP32 : P_FP64; ctrl->escalations += 1; }
+          else ctrl->status = ST_SINGULAR;
+        } else if (can_escalate && kappa >= tau_p) {
+          ctrl->cur_prec = (p == P_FP16) ? P_FP32 : P_FP64;
+          ctrl->escalations += 1;
+        }
+      }
+    }
+  }
+}
+
+// Stand-alone ICE of an upper-triangular matrix (one wave).
+__global__ void condest_kernel(const double* __restrict__ R, int n, int64_t ldr, double* __restrict__ kappa_out) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  double* Rl = reinterpret_cast<double*>(smem);
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int i = e % n, j = e / n;
+    Rl[e] = (i <= j) ? R[i + (int64_t)j * ldr] : 0.0;
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    double k = ice_kappa(Rl, n, 1, n);
+    if (threadIdx.x == 0) *kappa_out = k;
+  }
+}
+
+// Threads per column: a power of two <= 64 with tpc * n <= NT. Register
+// rows per thread RB >= ceil(s / tpc). Large RB runs with 512 threads so
+// that each thread may use 256 registers.
+static int qr_tpc(int n, int nt) {
+  int t = 64;
+  while (t > 1 && t * n > nt) t >>= 1;
+  return t;
+}
+
+size_t qr_smem_bytes(int s, int n, bool f64) {
+  const size_t el = f64 ? 8 : 4;
+  return (size_t)n * n * 8 + 2 * (size_t)s * el + 2 * el + (size_t)n * 4 + 64;
+}
+
+bool qr_supported(int s, int n) {
+  if (n < 1 || n > 128) return false;
+  const int tpc = qr_tpc(n, 512);
+  return (s + tpc - 1) / tpc <= 64;
+}
+
+template <typename T, int RB, int NT>
+static hipError_t launch_qr_rb(const double* Y, int s, int n, int64_t ldy, double* Rs, int64_t ldr,
+                               double* kappa, Ctrl* ctrl, int slot, int phase, hipStream_t st) {
+  const size_t sm = qr_smem_bytes(s, n, sizeof(T) == 8);
+  allow_dynamic_lds(reinterpret_cast<const void*>(&householder_kernel<T, RB, NT>), sm);
+  hipLaunchKernelGGL((householder_kernel<T, RB, NT>), dim3(1), dim3(NT), sm, st,
+                     Y, s, n, ldy, qr_tpc(n, NT), Rs, ldr, kappa, ctrl, slot, phase);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_qr_t(const double* Y, int s, int n, int64_t ldy, double* Rs, int64_t ldr,
+                              double* kappa, Ctrl* ctrl, int slot, int phase, hipStream_t st) {
+  const int t1 = qr_tpc(n, 1024);
+  const int need1 = (s + t1 - 1) / t1;
+  if (need1 <= 1) return launch_qr_rb<T, 1, 1024>(Y, s, n, ldy, Rs, ldr, kappa, ctrl, slot, phase, st);
+  if (need1 <= 2) return launch_qr_rb<T, 2, 1024>(Y, s, n, ldy, Rs, ldr, kappa, ctrl, slot, phase, st);
+  if (need1 <= 4) return launch_qr_rb<T, 4, 1024>(Y, s, n, ldy, Rs, ldr, kappa, ctrl, slot, phase, st);
+  if (need1 <= 8) return launch_qr_rb<T, 8, 1024>(Y, s, n, ldy, Rs, ldr, kappa, ctrl, slot, phase, st);
+  if (need1 <= 16) return launch_qr_rb<T, 16, 1024>(Y, s, n, ldy, Rs, ldr, kappa, ctrl, slot, phase, st);
+  const int t5 = qr_tpc(n, 512);
+  const int need5 = (s + t5 - 1) / t5;
+  if (need5 <= 32) return launch_qr_rb<T, 32, 512>(Y, s, n, ldy, Rs, ldr, kappa, ctrl, slot, phase, st);
+  if (need5 <= 64) return launch_qr_rb<T, 64, 512>(Y, s, n, ldy, Rs, ldr, kappa, ctrl, slot, phase, st);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_sketch_qr(bool f64, const double* Y, int s, int n, int64_t ldy, double* Rs, int64_t ldr,
+                            double* kappa, Ctrl* ctrl, int slot, int phase, hipStream_t st) {
+  return f64 ? launch_qr_t<double>(Y, s, n, ldy, Rs, ldr, kappa, ctrl, slot, phase, st)
+             : launch_qr_t<float>(Y, s, n, ldy, Rs, ldr, kappa, ctrl, slot, phase, st);
+}
+
+hipError_t launch_condest(const double* R, int n, int64_t ldr, double* kappa, hipStream_t st) {
+  allow_dynamic_lds(reinterpret_cast<const void*>(&condest_kernel), (size_t)n * n * 8);
+  hipLaunchKernelGGL(condest_kernel, dim3(1), dim3(256), (size_t)n * n * 8, st, R, n, ldr, kappa);
+  return hipGetLastError();
+}
+
+}  // namespace mrcqr

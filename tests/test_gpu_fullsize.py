@@ -1,0 +1,42 @@
+"""Full-size checks at m = 2^20, n = 128, s = 256 (the headline shape) in the
+launch configuration the bench times, on properties and sampled outputs:
+A = U (Sigma V^T) and Sigma V^T = Qt Rt give R = Rt and Q = U Qt exactly,
+so R and sampled rows of Q have a cheap reference."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import householder as HH, metrics as MT
+from gpu_common import require_gpu, to_dev, to_host, progress, torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def M():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def big():
+    m, n, kappa = 1 << 20, 128, 1e4
+    U, sig, V = W.test_matrix_factors(m, n, kappa, 11)
+    A = np.asfortranarray((U * sig[None, :]) @ V.T)
+    Qt, Rt = HH.householder_qr((sig[:, None] * V.T))
+    return A, U, Qt, Rt, kappa
+
+
+@pytest.mark.parametrize("prec", ["fp16", "fp64"])
+def test_headline_shape(M, big, prec):
+    A, U, Qt, Rt, kappa = big
+    m, n = A.shape
+    progress(f"full size {prec}")
+    Q, R, info = M.factor(to_dev(A), prec, seed=3)
+    assert info.status == 0, info
+    Qh, Rh = to_host(Q), to_host(R)
+    assert MT.orthogonality(Qh) <= 1e-13
+    assert MT.residual(A, Qh, Rh, 1.0) <= 1e-13
+    tol = 50 * n * 2.0 ** -53 * kappa
+    assert MT.rel_diff(Rh, Rt) <= tol
+    rows = np.random.default_rng(0).choice(m, 512, replace=False)
+    assert np.max(np.abs(Qh[rows] - U[rows] @ Qt)) <= tol
