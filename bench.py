@@ -106,13 +106,14 @@ def main() -> int:
     # dominant kernel: the float64 triangular solve X = A R^{-1} (launched twice per QR).
     Rs = torch.from_numpy(np.ascontiguousarray(np.triu(R.cpu().numpy()).T)).cuda().t()
     X = M.empty_colmajor(m, n)
+    tws = torch.empty(int(M.lib().mrcqr_trsm_workspace_bytes(n)), dtype=torch.uint8, device="cuda")
     for _ in range(3):
-        M.trsm(A, Rs, X)
+        M.trsm(A, Rs, X, workspace=tws)
     torch.cuda.synchronize()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     for e0, e1 in evs:
         e0.record(stream)
-        M.trsm(A, Rs, X)
+        M.trsm(A, Rs, X, workspace=tws)
         e1.record(stream)
     torch.cuda.synchronize()
     trsm_ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))

@@ -152,9 +152,14 @@ int mrcqr_sketch_qr(const double* Y, int64_t s, int64_t n, int64_t ldy, int qr_p
                     double* Rs, int64_t ldr, double* kappa_dev, void* stream);
 
 /* Stage 2 triangular solve X = A R^{-1} (R upper, n x n), by blocked
- * substitution (no inverse of R is formed). X must not overlap A. */
+ * substitution (no inverse of R is formed; Section "Algorithm
+ * Description"). X must not overlap A. Needs
+ * mrcqr_trsm_workspace_bytes(n) bytes of device workspace (R staged in
+ * operand order; about 75 KB at n = 128). */
+size_t mrcqr_trsm_workspace_bytes(int64_t n);
 int mrcqr_trsm(const double* A, int64_t m, int64_t n, int64_t lda,
-               const double* R, int64_t ldr, double* X, int64_t ldx, void* stream);
+               const double* R, int64_t ldr, double* X, int64_t ldx,
+               void* workspace, size_t workspace_bytes, void* stream);
 
 /* Algorithm 1 step 1: G = B^T B (n x n, both triangles written). Needs
  * mrcqr_gram_workspace_bytes(m, n) bytes of device workspace. */

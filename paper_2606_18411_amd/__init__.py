@@ -59,7 +59,8 @@ def lib() -> ctypes.CDLL:
             "mrcqr_sketch_workspace_bytes": (sz, [i64, i64, i64, i32]),
             "mrcqr_sketch": (i32, [vp, i64, i64, i64, vp, i64, u64, i32, vp, i64, vp, sz, vp]),
             "mrcqr_sketch_qr": (i32, [vp, i64, i64, i64, i32, vp, i64, vp, vp]),
-            "mrcqr_trsm": (i32, [vp, i64, i64, i64, vp, i64, vp, i64, vp]),
+            "mrcqr_trsm_workspace_bytes": (sz, [i64]),
+            "mrcqr_trsm": (i32, [vp, i64, i64, i64, vp, i64, vp, i64, vp, sz, vp]),
             "mrcqr_gram_workspace_bytes": (sz, [i64, i64]),
             "mrcqr_gram": (i32, [vp, i64, i64, i64, vp, i64, vp, sz, vp]),
             "mrcqr_cholesky": (i32, [vp, i64, i64, vp, i64, vp, vp, vp]),
@@ -246,12 +247,16 @@ def sketch_qr(Y: torch.Tensor, precision="fp32", stream=None):
     return Rs, kappa
 
 
-def trsm(A: torch.Tensor, R: torch.Tensor, X: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+def trsm(A: torch.Tensor, R: torch.Tensor, X: torch.Tensor | None = None, stream=None,
+         workspace: torch.Tensor | None = None) -> torch.Tensor:
     m, n = A.shape
     if X is None:
         X = empty_colmajor(m, n, A.device)
+    wsb = int(lib().mrcqr_trsm_workspace_bytes(n))
+    if workspace is None or workspace.numel() < wsb:
+        workspace = torch.empty(max(wsb, 1), dtype=torch.uint8, device=A.device)
     _check(lib().mrcqr_trsm(A.data_ptr(), m, n, _ld(A), R.data_ptr(), _ld(R), X.data_ptr(), _ld(X),
-                            _stream(stream)), "mrcqr_trsm")
+                            workspace.data_ptr(), wsb, _stream(stream)), "mrcqr_trsm")
     return X
 
 

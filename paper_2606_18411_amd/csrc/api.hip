@@ -18,7 +18,8 @@ hipError_t launch_sketch_qr(bool f64, const double* Y, int s, int n, int64_t ldy
 bool qr_supported(int s, int n);
 hipError_t launch_condest(const double* R, int n, int64_t ldr, double* kappa, hipStream_t st);
 hipError_t launch_trsm(const double* A, int m, int n, int64_t lda, const double* R, int64_t ldr,
-                       double* X, int64_t ldx, const Ctrl* ctrl, int phase, hipStream_t st);
+                       double* X, int64_t ldx, void* ws, const Ctrl* ctrl, int phase, hipStream_t st);
+size_t trsm_workspace_bytes(int n);
 hipError_t launch_gram(const double* B, int m, int n, int64_t ldb, double* Gpart, double* G, int64_t ldg,
                        const Ctrl* ctrl, int phase, hipStream_t st);
 size_t gram_partial_bytes(int64_t m, int64_t n);
@@ -61,7 +62,7 @@ int hip_status(hipError_t e) { return e == hipSuccess ? MRCQR_OK : MRCQR_ERR_DEV
 
 struct mrcqr_plan {
   int64_t m, n, s;
-  size_t off_ctrl, off_S, off_Ypart, off_Y, off_Rs, off_Gpart, off_G, off_Rc, off_B, total;
+  size_t off_ctrl, off_S, off_Ypart, off_Y, off_Rs, off_Gpart, off_G, off_Rc, off_Tw, off_B, total;
 };
 
 static void plan_layout(mrcqr_plan* p) {
@@ -76,6 +77,7 @@ static void plan_layout(mrcqr_plan* p) {
   p->off_Gpart = take(gram_partial_bytes(p->m, p->n));
   p->off_G = take(n * n * sizeof(double));
   p->off_Rc = take(n * n * sizeof(double));
+  p->off_Tw = take(trsm_workspace_bytes((int)n));
   p->off_B = take(m * n * sizeof(double));
   p->total = o;
 }
@@ -92,6 +94,7 @@ static int execute(const mrcqr_plan* p, char* ws, const double* A, int64_t lda, 
   double* G = reinterpret_cast<double*>(ws + p->off_G);
   double* Rc = reinterpret_cast<double*>(ws + p->off_Rc);
   double* B = reinterpret_cast<double*>(ws + p->off_B);
+  void* Tw = ws + p->off_Tw;
   const int64_t ldb = p->m;
   hipError_t e;
   const bool automode = prec == MRCQR_PREC_AUTO;
@@ -105,10 +108,10 @@ static int execute(const mrcqr_plan* p, char* ws, const double* A, int64_t lda, 
            launch_sketch_qr(pp == P_FP64, Y, s, n, s, Rs, n, nullptr, ctrl, pp, phase, st) == hipSuccess;
   };
   auto stage2 = [&](int phase, int tail_phase) -> bool {
-    return launch_trsm(A, m, n, lda, Rs, n, B, ldb, ctrl, phase, st) == hipSuccess &&
+    return launch_trsm(A, m, n, lda, Rs, n, B, ldb, Tw, ctrl, phase, st) == hipSuccess &&
            launch_gram(B, m, n, ldb, Gpart, G, n, ctrl, phase, st) == hipSuccess &&
            launch_cholesky(G, n, n, Rc, n, nullptr, nullptr, ctrl, phase, st) == hipSuccess &&
-           launch_trsm(B, m, n, ldb, Rc, n, Q, ldq, ctrl, tail_phase, st) == hipSuccess &&
+           launch_trsm(B, m, n, ldb, Rc, n, Q, ldq, Tw, ctrl, tail_phase, st) == hipSuccess &&
            launch_trmm(Rc, n, Rs, n, n, R, ldr, ctrl, tail_phase, st) == hipSuccess;
   };
   if (automode) {
@@ -250,11 +253,18 @@ int mrcqr_sketch_qr(const double* Y, int64_t s, int64_t n, int64_t ldy, int qr_p
                                      nullptr, P_AUTO, PH_FIRST, as_stream(stream)));
 }
 
+size_t mrcqr_trsm_workspace_bytes(int64_t n) {
+  if (n < 1 || n > NMAX) return 0;
+  return trsm_workspace_bytes((int)n);
+}
+
 int mrcqr_trsm(const double* A, int64_t m, int64_t n, int64_t lda, const double* R, int64_t ldr, double* X,
-               int64_t ldx, void* stream) {
+               int64_t ldx, void* workspace, size_t workspace_bytes, void* stream) {
   if (!A || !R || !X || m < 1 || n < 1 || lda < m || ldr < n || ldx < m || A == X) return MRCQR_ERR_ARG;
   if (n > NMAX || m >= MMAX) return MRCQR_ERR_UNSUPPORTED;
-  return hip_status(launch_trsm(A, (int)m, (int)n, lda, R, ldr, X, ldx, nullptr, PH_FIRST, as_stream(stream)));
+  if (!workspace || workspace_bytes < trsm_workspace_bytes((int)n)) return MRCQR_ERR_WORKSPACE;
+  return hip_status(launch_trsm(A, (int)m, (int)n, lda, R, ldr, X, ldx, workspace, nullptr, PH_FIRST,
+                                as_stream(stream)));
 }
 
 size_t mrcqr_gram_workspace_bytes(int64_t m, int64_t n) {

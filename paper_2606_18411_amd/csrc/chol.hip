@@ -10,9 +10,13 @@
 
 namespace mrcqr {
 
-constexpr int CH_THREADS = 1024;
+constexpr int CH_THREADS = 512;
 
 // Right-looking Cholesky of the upper triangle of G, held row-major in LDS.
+// Step j keeps row j unscaled and updates the trailing triangle with
+// L[i][k] -= L[j][i] * L[j][k] / piv_j (one barrier per step); the rows are
+// scaled by 1/sqrt(piv) at the end, which gives the textbook
+// R[j][k] = (G[j][k] - sum_i R[i][j] R[i][k]) / R[j][j].
 __global__ __launch_bounds__(CH_THREADS) void chol_kernel(
     const double* __restrict__ G, int n, int64_t ldg, double* __restrict__ Rc, int64_t ldr,
     int32_t* __restrict__ fail_out, double* __restrict__ kappa_out, Ctrl* __restrict__ ctrl, int phase) {
@@ -20,37 +24,32 @@ __global__ __launch_bounds__(CH_THREADS) void chol_kernel(
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   double* L = reinterpret_cast<double*>(smem);
   const int ld = n + 1;
-  __shared__ int fail;
   const int tid = threadIdx.x;
-  for (int e = tid; e < n * n; e += CH_THREADS) {
-    const int i = e / n, k = e % n;
-    L[i * ld + k] = (i <= k) ? G[i + (int64_t)k * ldg] : 0.0;
-  }
-  if (tid == 0) fail = -1;
+  const int tx = tid & 63, ty = tid >> 6;   // ty is wave-uniform
+  constexpr int TY = CH_THREADS / 64;
+  for (int k = tx; k < n; k += 64)
+    for (int i = ty; i < n; i += TY) L[i * ld + k] = (i <= k) ? G[i + (int64_t)k * ldg] : 0.0;
   __syncthreads();
+  int f = -1;
   for (int j = 0; j < n; ++j) {
-    if (tid == 0) {
-      const double piv = L[j * ld + j];
-      if (!(piv > 0.0) || !isfinite(piv)) fail = j;
-      else L[j * ld + j] = sqrt(piv);
-    }
-    __syncthreads();
-    if (fail >= 0) break;
-    const double rjj = L[j * ld + j];
-    for (int k = j + 1 + tid; k < n; k += CH_THREADS) L[j * ld + k] = L[j * ld + k] / rjj;
-    __syncthreads();
-    const int w = n - j - 1;
-    for (int e = tid; e < w * w; e += CH_THREADS) {
-      const int i = j + 1 + e / w, k = j + 1 + e % w;
-      if (k >= i) L[i * ld + k] = fma(-L[j * ld + i], L[j * ld + k], L[i * ld + k]);
+    const double piv = L[j * ld + j];
+    if (!(piv > 0.0) || !isfinite(piv)) { f = j; break; }
+    const double inv = 1.0 / piv;
+    for (int k = j + 1 + tx; k < n; k += 64) {
+      const double ljk = L[j * ld + k] * inv;
+      for (int i = j + 1 + ty; i <= k; i += TY) L[i * ld + k] = fma(-L[j * ld + i], ljk, L[i * ld + k]);
     }
     __syncthreads();
   }
-  const int f = fail;
-  for (int e = tid; e < n * n; e += CH_THREADS) {
-    const int i = e % n, k = e / n;
-    Rc[i + (int64_t)k * ldr] = (f < 0 && i <= k) ? L[i * ld + k] : 0.0;
+  // scale rows: R[j][k] = L[j][k] / sqrt(L[j][j])
+  const int nrows = (f < 0) ? n : f;
+  for (int i = ty; i < nrows; i += TY) {
+    const double rinv = 1.0 / sqrt(L[i * ld + i]);
+    for (int k = i + tx; k < n; k += 64) L[i * ld + k] = (k == i) ? sqrt(L[i * ld + i]) : L[i * ld + k] * rinv;
   }
+  __syncthreads();
+  for (int k = tx; k < n; k += 64)
+    for (int i = ty; i < n; i += TY) Rc[i + (int64_t)k * ldr] = (f < 0 && i <= k) ? L[i * ld + k] : 0.0;
   if (tid < 64) {
     double kappa = __builtin_inf();
     if (f < 0) kappa = ice_kappa(L, n, ld, 1);

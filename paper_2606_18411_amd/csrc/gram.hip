@@ -75,18 +75,43 @@ __global__ __launch_bounds__(GR_THREADS) void syrk_kernel(
   }
 }
 
-// G[i, j] = G[j, i] = sum over chunks (fixed order) of the upper partial (i <= j).
-__global__ void gram_reduce_kernel(const double* __restrict__ Gpart, int chunks, int n,
-                                   double* __restrict__ G, int64_t ldg, const Ctrl* __restrict__ ctrl, int phase) {
+// G[i, j] = G[j, i] = sum over chunks of the upper partial (i <= j). One
+// block per column j; its 4 waves sum 4 contiguous chunk ranges (lanes over
+// rows i), combined in LDS in fixed order (deterministic).
+__global__ __launch_bounds__(256) void gram_reduce_kernel(const double* __restrict__ Gpart, int chunks, int n,
+                                                          double* __restrict__ G, int64_t ldg,
+                                                          const Ctrl* __restrict__ ctrl, int phase) {
   if (skip_launch(ctrl, P_AUTO, phase)) return;
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= n * n) return;
-  const int i = idx % n, j = idx / n;
-  if (i > j) return;
-  double acc = 0.0;
-  for (int k = 0; k < chunks; ++k) acc += Gpart[(int64_t)k * n * n + (int64_t)j * n + i];
-  G[i + (int64_t)j * ldg] = acc;
-  G[j + (int64_t)i * ldg] = acc;
+  __shared__ double part[4][64];
+  const int j = blockIdx.x;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int per = (chunks + 3) / 4;
+  const int c0 = w * per, c1 = min(chunks, c0 + per);
+  for (int i0 = 0; i0 <= j; i0 += 64) {
+    const int i = i0 + l;
+    double acc = 0.0;
+    if (i <= j) {
+      const double* p = Gpart + (int64_t)j * n + i;
+      const int64_t str = (int64_t)n * n;
+      int c = c0;
+      for (; c + 8 <= c1; c += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = p[(int64_t)(c + u) * str];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += v[u];
+      }
+      for (; c < c1; ++c) acc += p[(int64_t)c * str];
+    }
+    part[w][l] = acc;
+    __syncthreads();
+    if (w == 0 && i <= j) {
+      const double tot = ((part[0][l] + part[1][l]) + part[2][l]) + part[3][l];
+      G[i + (int64_t)j * ldg] = tot;
+      G[j + (int64_t)i * ldg] = tot;
+    }
+    __syncthreads();
+  }
 }
 
 struct GramGeom { int chunks, rows_per_chunk; };
@@ -111,8 +136,7 @@ hipError_t launch_gram(const double* B, int m, int n, int64_t ldb, double* Gpart
   if (n > GR_NMAX) return hipErrorInvalidValue;
   GramGeom gg = gram_geometry(m);
   hipLaunchKernelGGL(syrk_kernel, dim3(gg.chunks), dim3(GR_THREADS), 0, st, B, m, n, ldb, gg.rows_per_chunk, Gpart, ctrl, phase);
-  const int tot = n * n;
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3((tot + 255) / 256), dim3(256), 0, st, (const double*)Gpart, gg.chunks, n, G, ldg, ctrl, phase);
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3(n), dim3(256), 0, st, (const double*)Gpart, gg.chunks, n, G, ldg, ctrl, phase);
   return hipGetLastError();
 }
 

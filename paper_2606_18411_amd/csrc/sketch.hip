@@ -305,22 +305,44 @@ __global__ __launch_bounds__(SK_THREADS) void sketch_kernel(
     }
 }
 
-// Y[srow, col] = gamma_k * sum over chunks (fixed order, float64), then
-// rounded to float32 for the low-precision sketches.
+// Y[srow, col] = gamma_k * sum over chunks (float64, fixed order), then
+// rounded to float32 for the low-precision sketches. A block covers 64
+// consecutive (col, srow) entries; its 4 waves sum 4 contiguous chunk
+// ranges, combined in LDS in fixed order.
 template <typename AccT>
-__global__ void sketch_reduce_kernel(const AccT* __restrict__ Ypart, int chunks, int n, int s,
+__global__ __launch_bounds__(256) void sketch_reduce_kernel(const AccT* __restrict__ Ypart, int chunks, int n, int s,
                                      const int32_t* __restrict__ S, double* __restrict__ Y, int64_t ldy,
                                      int round_f32, const Ctrl* __restrict__ ctrl, int slot, int phase) {
   if (skip_launch(ctrl, slot, phase)) return;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)n * s) return;
-  const int col = (int)(idx / s), srow = (int)(idx % s);
+  __shared__ double part[4][64];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int64_t idx = (int64_t)blockIdx.x * 64 + l;
+  const int64_t tot = (int64_t)n * s;
+  const int per = (chunks + 3) / 4;
+  const int c0 = w * per, c1 = min(chunks, c0 + per);
   double acc = 0.0;
-  for (int c = 0; c < chunks; ++c) acc += (double)Ypart[((int64_t)c * n + col) * s + srow];
-  const double gamma = (S[srow] == 0) ? sqrt(1.0 / (double)s) : sqrt(2.0 / (double)s);
-  double y = gamma * acc;
-  if (round_f32) y = (double)(float)y;
-  Y[srow + (int64_t)col * ldy] = y;
+  if (idx < tot) {
+    const AccT* p = Ypart + idx;
+    int c = c0;
+    for (; c + 8 <= c1; c += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = (double)p[(int64_t)(c + u) * tot];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    for (; c < c1; ++c) acc += (double)p[(int64_t)c * tot];
+  }
+  part[w][l] = acc;
+  __syncthreads();
+  if (w == 0 && idx < tot) {
+    const int col = (int)(idx / s), srow = (int)(idx % s);
+    const double sum = ((part[0][l] + part[1][l]) + part[2][l]) + part[3][l];
+    const double gamma = (S[srow] == 0) ? sqrt(1.0 / (double)s) : sqrt(2.0 / (double)s);
+    double y = gamma * sum;
+    if (round_f32) y = (double)(float)y;
+    Y[srow + (int64_t)col * ldy] = y;
+  }
 }
 
 // ---- host-side launch -------------------------------------------------
@@ -350,7 +372,7 @@ hipError_t launch_sketch(int prec, const double* A, int64_t lda, int m, int n, c
   dim3 block(SK_THREADS);
   const int rb = 256;
   const int64_t tot = (int64_t)n * s;
-  dim3 rgrid((unsigned)((tot + rb - 1) / rb));
+  dim3 rgrid((unsigned)((tot + 63) / 64));
   switch (prec) {
     case P_FP16:
       hipLaunchKernelGGL(sketch_kernel<P_FP16>, grid, block, 0, st, A, lda, m, n, S, s, seed, gg.rows_per_chunk, (float*)Ypart, ctrl, phase);

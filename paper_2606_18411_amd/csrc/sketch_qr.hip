@@ -35,8 +35,8 @@ __global__ __launch_bounds__(NT) void householder_kernel(
   if (skip_launch(ctrl, slot, phase)) return;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   double* Rl = reinterpret_cast<double*>(smem);          // n * n, column-major
-  T* vbuf = reinterpret_cast<T*>(Rl + (size_t)n * n);    // 2 * s
-  T* taus = vbuf + 2 * s;                                // 2
+  T* vbuf = reinterpret_cast<T*>(Rl + (size_t)n * n);    // 2 * tpc * RB
+  T* taus = vbuf + 2 * tpc * RB;                         // 2
   float* dsign = reinterpret_cast<float*>(taus + 2);     // n
   __shared__ int bad_flag;
 
@@ -72,21 +72,23 @@ __global__ __launch_bounds__(NT) void householder_kernel(
 #pragma unroll
   for (int i = 0; i < RB; ++i) y[i] = (T)ldexp((double)y[i], es);
 
+  // Branch-free column loop: the reflector buffer has tpc * RB entries
+  // (zero for rows >= s and rows < j), so every thread runs the same
+  // straight-line code over its RB rows.
+  const int vlen = tpc * RB;
   for (int j = 0; j < n; ++j) {
     const int buf = j & 1;
-    T* v = vbuf + buf * s;
+    T* v = vbuf + buf * vlen;
     if (c == j) {
-      const int rb0 = j % tpc, i0 = j / tpc;
       T alpha_l = (T)0, sp[4] = {(T)0, (T)0, (T)0, (T)0};
 #pragma unroll
       for (int i = 0; i < RB; ++i) {
         const int r = rb + tpc * i;
-        if (r == j) alpha_l = y[i];
-        if (r > j && r < s) sp[i & 3] += y[i] * y[i];
+        alpha_l = (r == j) ? y[i] : alpha_l;
+        sp[i & 3] += (r > j) ? y[i] * y[i] : (T)0;
       }
-      T sig = (sp[0] + sp[1]) + (sp[2] + sp[3]);
-      const T alpha = group_sum(alpha_l, tpc);  // only lane rb0 contributes
-      sig = group_sum(sig, tpc);
+      const T alpha = group_sum(alpha_l, tpc);  // only the lane holding row j contributes
+      const T sig = group_sum((sp[0] + sp[1]) + (sp[2] + sp[3]), tpc);
       T tau, beta, scal;
       if (sig == (T)0) { tau = (T)0; beta = alpha; scal = (T)0; }
       else {
@@ -98,31 +100,24 @@ __global__ __launch_bounds__(NT) void householder_kernel(
 #pragma unroll
       for (int i = 0; i < RB; ++i) {
         const int r = rb + tpc * i;
-        if (r < s) v[r] = (r > j) ? y[i] * scal : (r == j ? (T)1 : (T)0);
-        if (r == j) y[i] = beta;
+        v[r] = (r > j) ? y[i] * scal : (r == j ? (T)1 : (T)0);
+        y[i] = (r == j) ? beta : y[i];
       }
-      if (rb == rb0) taus[buf] = tau;
-      (void)i0;
+      if (rb == 0) taus[buf] = tau;
     }
     __syncthreads();
     if (active && c > j) {
       const T tau = taus[buf];
-      if (tau != (T)0) {
-        T dp[4] = {(T)0, (T)0, (T)0, (T)0};
+      T vv[RB];
 #pragma unroll
-        for (int i = 0; i < RB; ++i) {
-          const int r = rb + tpc * i;
-          if (r >= j && r < s) dp[i & 3] += v[r] * y[i];
-        }
-        T d = (dp[0] + dp[1]) + (dp[2] + dp[3]);
-        d = group_sum(d, tpc);
-        const T f = tau * d;
+      for (int i = 0; i < RB; ++i) vv[i] = v[rb + tpc * i];
+      T dp[4] = {(T)0, (T)0, (T)0, (T)0};
 #pragma unroll
-        for (int i = 0; i < RB; ++i) {
-          const int r = rb + tpc * i;
-          if (r >= j && r < s) y[i] -= f * v[r];
-        }
-      }
+      for (int i = 0; i < RB; ++i) dp[i & 3] += vv[i] * y[i];
+      const T d = group_sum((dp[0] + dp[1]) + (dp[2] + dp[3]), tpc);
+      const T f = tau * d;
+#pragma unroll
+      for (int i = 0; i < RB; ++i) y[i] -= f * vv[i];
     }
   }
 
@@ -194,9 +189,9 @@ static int qr_tpc(int n, int nt) {
   return t;
 }
 
-size_t qr_smem_bytes(int s, int n, bool f64) {
+size_t qr_smem_bytes(int vlen, int n, bool f64) {
   const size_t el = f64 ? 8 : 4;
-  return (size_t)n * n * 8 + 2 * (size_t)s * el + 2 * el + (size_t)n * 4 + 64;
+  return (size_t)n * n * 8 + 2 * (size_t)vlen * el + 2 * el + (size_t)n * 4 + 64;
 }
 
 bool qr_supported(int s, int n) {
@@ -208,7 +203,7 @@ bool qr_supported(int s, int n) {
 template <typename T, int RB, int NT>
 static hipError_t launch_qr_rb(const double* Y, int s, int n, int64_t ldy, double* Rs, int64_t ldr,
                                double* kappa, Ctrl* ctrl, int slot, int phase, hipStream_t st) {
-  const size_t sm = qr_smem_bytes(s, n, sizeof(T) == 8);
+  const size_t sm = qr_smem_bytes(qr_tpc(n, NT) * RB, n, sizeof(T) == 8);
   allow_dynamic_lds(reinterpret_cast<const void*>(&householder_kernel<T, RB, NT>), sm);
   hipLaunchKernelGGL((householder_kernel<T, RB, NT>), dim3(1), dim3(NT), sm, st,
                      Y, s, n, ldy, qr_tpc(n, NT), Rs, ldr, kappa, ctrl, slot, phase);

@@ -4,121 +4,169 @@
 // product with an explicitly inverted Rs (Section "Algorithm Description"),
 // so every 16 x 16 diagonal block is handled by substitution.
 //
-// Each wave owns 32 rows. Columns go in blocks J of 16. For block J the
-// wave computes, in the transposed form X_J^T = R_JJ^{-T}(A_J^T -
-// R_{<J,J}^T X_{<J}^T), the update as float64 MFMA 16x16x4 with the
-// negated off-diagonal blocks of R (staged once per workgroup in LDS) as A
-// operand and the already solved columns (kept in registers in B-operand
-// layout) as B operand; the result goes through a per-wave LDS tile into
-// one-row-per-lane layout, where lanes 0..31 run the forward substitution
-// with the diagonal block (uniform, scalar-loaded entries of R and
-// reciprocals of its diagonal), and back into B-operand registers and to X.
+// A prep kernel stages R once per call into two padded, pre-negated operand
+// arrays (no bound checks remain in the main loop):
+//   Rop: off-diagonal blocks in MFMA A-operand order,
+//        Rop[off(J, q) + lane] = -R[4q + lane/16][16J + lane%16];
+//   Dg:  diagonal blocks row-major, Dg[J][k][j] = -R[16J+k][16J+j] (j > k),
+//        1/R[16J+k][16J+k] on the diagonal, zero elsewhere and beyond n.
+// Main kernel: each wave owns 64 rows (4 row tiles of 16). Columns go in
+// blocks J of 16. In the transposed form X_J^T = R_JJ^{-T}(A_J^T -
+// R_{<J,J}^T X_{<J}^T) the update runs as float64 MFMA 16x16x4 with Rop
+// (staged in LDS) as A operand and the solved columns (kept in registers in
+// B-operand layout) as B operand. The result goes through a per-wave LDS
+// tile to one row per lane, the 64 lanes run the forward substitution with
+// wave-uniform diagonal-block rows (scalar loads), and the solved columns
+// return to B-operand registers and to X.
 #include "common.hpp"
 
 namespace mrcqr {
 
 constexpr int TR_THREADS = 256;
-constexpr int TR_ROWS = 128;  // rows per workgroup pass (4 waves x 32)
-constexpr int TR_TLD = 17;    // leading dimension of the per-wave LDS tile
+constexpr int TR_WROWS = 64;                 // rows per wave
+constexpr int TR_ROWS = 4 * TR_WROWS;        // rows per workgroup pass
+constexpr int TR_TLD = 17;                   // leading dimension of the per-wave LDS tile
+constexpr int TR_NMAX = 128;
 
 __host__ __device__ constexpr int tr_off(int J, int q) { return 64 * (2 * J * (J - 1) + q); }
+__host__ __device__ constexpr int tr_rop_size(int nb) { return nb > 1 ? tr_off(nb, 0) : 64; }
+
+size_t trsm_workspace_bytes(int n) {
+  const int nb = (n + 15) / 16;
+  return ((size_t)tr_rop_size(nb) + (size_t)nb * 256) * sizeof(double) + 256;
+}
+
+__global__ void trsm_prep_kernel(const double* __restrict__ R, int n, int64_t ldr, double* __restrict__ Rop,
+                                 double* __restrict__ Dg, const Ctrl* __restrict__ ctrl, int phase) {
+  if (skip_launch(ctrl, P_AUTO, phase)) return;
+  const int nb = (n + 15) / 16;
+  const int nrop = tr_rop_size(nb);
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nrop + nb * 256; e += gridDim.x * blockDim.x) {
+    if (e < nrop) {
+      // invert off(J, q) + lane
+      int J = 1;
+      while (J < nb && e >= tr_off(J + 1, 0)) ++J;
+      const int rem = e - tr_off(J, 0);
+      const int q = rem / 64, lane = rem % 64;
+      const int row = 4 * q + lane / 16, col = 16 * J + lane % 16;
+      Rop[e] = (nb > 1 && row < n && col < n) ? -R[row + (int64_t)col * ldr] : 0.0;
+    } else {
+      const int d = e - nrop;
+      const int J = d / 256, k = (d % 256) / 16, j = d % 16;
+      const int row = 16 * J + k, col = 16 * J + j;
+      double v = 0.0;
+      if (row < n && col < n) {
+        if (j > k) v = -R[row + (int64_t)col * ldr];
+        else if (j == k) v = 1.0 / R[row + (int64_t)row * ldr];
+      }
+      Dg[d] = v;
+    }
+  }
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 template <int NMAX>
 __global__ __launch_bounds__(TR_THREADS) void trsm_kernel(
     const double* __restrict__ A, int m, int n, int64_t lda,
-    const double* __restrict__ R, int64_t ldr, double* __restrict__ X, int64_t ldx,
-    const Ctrl* __restrict__ ctrl, int phase) {
+    const double* __restrict__ Rop, const double* __restrict__ Dg,
+    double* __restrict__ X, int64_t ldx, const Ctrl* __restrict__ ctrl, int phase) {
   constexpr int NB = NMAX / 16;
-  constexpr int RSZ = (NB > 1) ? tr_off(NB, 0) : 64;
-  __shared__ double Rl[RSZ];
-  __shared__ double invd[NMAX];
-  __shared__ double Tt[4][32 * TR_TLD];
+  constexpr int RSZ = tr_rop_size(NB);
+  __shared__ __attribute__((aligned(16))) double Rl[RSZ];
+  __shared__ double Tt[4][TR_WROWS * TR_TLD];
   if (skip_launch(ctrl, P_AUTO, phase)) return;
 
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63, g = l >> 4, c16 = l & 15;
   const int nb = (n + 15) / 16;
-
-  // stage -R[4q + g][16J + c16] for J >= 1, q < 4J (zero outside n x n)
-  for (int J = 1; J < nb; ++J)
-    for (int q = w; q < 4 * J; q += 4) {
-      const int row = 4 * q + g, col = 16 * J + c16;
-      Rl[tr_off(J, q) + l] = (row < n && col < n) ? -R[row + (int64_t)col * ldr] : 0.0;
-    }
-  for (int j = tid; j < NMAX; j += TR_THREADS) invd[j] = (j < n) ? 1.0 / R[j + (int64_t)j * ldr] : 0.0;
+  const int rsz = tr_rop_size(nb);
+  for (int e = tid; e < rsz; e += TR_THREADS) Rl[e] = Rop[e];
   __syncthreads();
 
   double* Tw = Tt[w];
   for (int64_t pan = blockIdx.x; pan * TR_ROWS < m; pan += gridDim.x) {
-    const int64_t r0 = pan * TR_ROWS + 32 * w;
-    double xb[4 * NB][2];
+    const int64_t r0 = pan * TR_ROWS + TR_WROWS * w;
+    double xb[4 * NB][4];
+    double an[4][4];
+    auto load_a = [&](int J) {
 #pragma unroll
-    for (int J = 0; J < NB; ++J) {
-      if (J >= nb) break;
-      f64x4 acc[2];
-#pragma unroll
-      for (int nt = 0; nt < 2; ++nt)
+      for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int64_t row = r0 + 16 * nt + c16;
           const int col = 16 * J + d_row_f64(l, r);
-          acc[nt][r] = (row < m && col < n) ? A[row + (int64_t)col * lda] : 0.0;
+          an[nt][r] = (row < m && col < n) ? A[row + (int64_t)col * lda] : 0.0;
         }
+    };
+    load_a(0);
+#pragma unroll
+    for (int J = 0; J < NB; ++J) {
+      if (J >= nb) break;
+      f64x4 acc[4];
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) acc[nt] = f64x4{an[nt][0], an[nt][1], an[nt][2], an[nt][3]};
+      if (J + 1 < nb) load_a(J + 1);
 #pragma unroll
       for (int q = 0; q < 4 * J; ++q) {
         const double ra = Rl[tr_off(J, q) + l];
-        acc[0] = mfma_f64(ra, xb[q][0], acc[0]);
-        acc[1] = mfma_f64(ra, xb[q][1], acc[1]);
-      }
-      // transpose through LDS: Tw[row_local][col_local]
 #pragma unroll
-      for (int nt = 0; nt < 2; ++nt)
+        for (int nt = 0; nt < 4; ++nt) acc[nt] = mfma_f64(ra, xb[q][nt], acc[nt]);
+      }
+      // to one row per lane: Tw[row_local][col_local]
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt)
 #pragma unroll
         for (int r = 0; r < 4; ++r) Tw[(16 * nt + c16) * TR_TLD + d_row_f64(l, r)] = acc[nt][r];
-      __syncthreads();
-      if (l < 32) {
-        double y[16];
+      wave_lds_sync();
+      double y[16];
 #pragma unroll
-        for (int k = 0; k < 16; ++k) y[k] = Tw[l * TR_TLD + k];
-        const int base = 16 * J;
+      for (int k = 0; k < 16; ++k) y[k] = Tw[l * TR_TLD + k];
+      const double* Dr = Dg + J * 256;
 #pragma unroll
-        for (int k = 0; k < 16; ++k) {
-          if (base + k < n) {
-            const double xk = y[k] * invd[base + k];
-            y[k] = xk;
+      for (int k = 0; k < 16; ++k) {
+        const double xk = y[k] * Dr[17 * k];
+        y[k] = xk;
 #pragma unroll
-            for (int jj = k + 1; jj < 16; ++jj)
-              if (base + jj < n) y[jj] = fma(-xk, R[(base + k) + (int64_t)(base + jj) * ldr], y[jj]);
-          }
-        }
-#pragma unroll
-        for (int k = 0; k < 16; ++k) Tw[l * TR_TLD + k] = y[k];
+        for (int jj = k + 1; jj < 16; ++jj) y[jj] = fma(xk, Dr[16 * k + jj], y[jj]);
       }
-      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < 16; ++k) Tw[l * TR_TLD + k] = y[k];
+      wave_lds_sync();
 #pragma unroll
       for (int qq = 0; qq < 4; ++qq)
 #pragma unroll
-        for (int nt = 0; nt < 2; ++nt) {
+        for (int nt = 0; nt < 4; ++nt) {
           const double v = Tw[(16 * nt + c16) * TR_TLD + 4 * qq + g];
           xb[4 * J + qq][nt] = v;
           const int64_t row = r0 + 16 * nt + c16;
           const int col = 16 * J + 4 * qq + g;
           if (row < m && col < n) X[row + (int64_t)col * ldx] = v;
         }
-      __syncthreads();
+      wave_lds_sync();
     }
   }
 }
 
 hipError_t launch_trsm(const double* A, int m, int n, int64_t lda, const double* R, int64_t ldr,
-                       double* X, int64_t ldx, const Ctrl* ctrl, int phase, hipStream_t st) {
+                       double* X, int64_t ldx, void* ws, const Ctrl* ctrl, int phase, hipStream_t st) {
+  if (n > TR_NMAX) return hipErrorInvalidValue;
+  const int nb = (n + 15) / 16;
+  double* Rop = static_cast<double*>(ws);
+  double* Dg = Rop + tr_rop_size(nb);
+  const int prep_elems = tr_rop_size(nb) + nb * 256;
+  hipLaunchKernelGGL(trsm_prep_kernel, dim3((prep_elems + 255) / 256), dim3(256), 0, st, R, n, ldr, Rop, Dg,
+                     ctrl, phase);
   const int64_t panels = ((int64_t)m + TR_ROWS - 1) / TR_ROWS;
-  const int grid = (int)(panels < 1024 ? panels : 1024);
-  if (grid < 1) return hipSuccess;
-  if (n <= 32) hipLaunchKernelGGL(trsm_kernel<32>, dim3(grid), dim3(TR_THREADS), 0, st, A, m, n, lda, R, ldr, X, ldx, ctrl, phase);
-  else if (n <= 64) hipLaunchKernelGGL(trsm_kernel<64>, dim3(grid), dim3(TR_THREADS), 0, st, A, m, n, lda, R, ldr, X, ldx, ctrl, phase);
-  else if (n <= 128) hipLaunchKernelGGL(trsm_kernel<128>, dim3(grid), dim3(TR_THREADS), 0, st, A, m, n, lda, R, ldr, X, ldx, ctrl, phase);
-  else return hipErrorInvalidValue;
+  const int grid = (int)(panels < 512 ? panels : 512);
+  if (grid < 1) return hipGetLastError();
+  if (n <= 32) hipLaunchKernelGGL(trsm_kernel<32>, dim3(grid), dim3(TR_THREADS), 0, st, A, m, n, lda, Rop, Dg, X, ldx, ctrl, phase);
+  else if (n <= 64) hipLaunchKernelGGL(trsm_kernel<64>, dim3(grid), dim3(TR_THREADS), 0, st, A, m, n, lda, Rop, Dg, X, ldx, ctrl, phase);
+  else hipLaunchKernelGGL(trsm_kernel<128>, dim3(grid), dim3(TR_THREADS), 0, st, A, m, n, lda, Rop, Dg, X, ldx, ctrl, phase);
   return hipGetLastError();
 }
 
