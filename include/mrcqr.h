@@ -76,7 +76,9 @@ typedef struct mrcqr_info {
   int32_t precision_used;  /* mrcqr_precision of the accepted Stage 1          */
   int32_t chol_fail_index; /* first failing pivot, or -1                       */
   int32_t escalations;     /* AUTO: number of precision escalations            */
-  double kappa_rs_est;     /* ICE estimate of kappa_2(Rs) (a lower bound)      */
+  double kappa_rs_est;     /* ICE estimate of kappa_2(Rs) (a lower bound); only
+                              AUTO computes it: NaN for a forced precision,
+                              +inf when Rs was singular                      */
   double kappa_rc_est;     /* ICE estimate of kappa_2(Rc) = kappa_2(B)         */
 } mrcqr_info;
 

@@ -103,4 +103,63 @@ inline void allow_dynamic_lds(const void* fn, size_t bytes) {
   }
 }
 
+// ---- wave-level reductions on DPP (no LDS crossbar round trips) ---------
+// DPP controls (GFX9 encoding): quad_perm [1,0,3,2] = 0xB1, [2,3,0,1] = 0x4E,
+// row_half_mirror = 0x141, row_mirror = 0x140. After the four stages every
+// lane holds the sum over its aligned group of 16 lanes.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <typename T>
+__device__ __forceinline__ T dpp_t(T v, int stage) {
+  if constexpr (sizeof(T) == 4) {
+    switch (stage) { case 0: return dpp_f32<0xB1>(v); case 1: return dpp_f32<0x4E>(v);
+                     case 2: return dpp_f32<0x141>(v); default: return dpp_f32<0x140>(v); }
+  } else {
+    switch (stage) { case 0: return dpp_f64<0xB1>(v); case 1: return dpp_f64<0x4E>(v);
+                     case 2: return dpp_f64<0x141>(v); default: return dpp_f64<0x140>(v); }
+  }
+}
+template <typename T>
+__device__ __forceinline__ T readlane_t(T v, int lane) {
+  if constexpr (sizeof(T) == 4) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+  } else {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+  }
+}
+// Sum over aligned groups of g lanes (g a power of two, 1..64); every lane
+// of a group receives the group's sum. Summation order is fixed.
+template <typename T>
+__device__ __forceinline__ T group_sum_dpp(T v, int g) {
+  if (g >= 2) v += dpp_t(v, 0);
+  if (g >= 4) v += dpp_t(v, 1);
+  if (g >= 8) v += dpp_t(v, 2);
+  if (g >= 16) v += dpp_t(v, 3);
+  if (g >= 32) {
+    const T r0 = readlane_t(v, 0), r1 = readlane_t(v, 16), r2 = readlane_t(v, 32), r3 = readlane_t(v, 48);
+    if (g == 32) v = ((threadIdx.x & 63) < 32) ? (r0 + r1) : (r2 + r3);
+    else v = (r0 + r1) + (r2 + r3);
+  }
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_sum_dpp(T v) { return group_sum_dpp(v, 64); }
+// Max over aligned groups of 8 lanes.
+__device__ __forceinline__ double group8_max_dpp(double v) {
+  v = fmax(v, dpp_t(v, 0));
+  v = fmax(v, dpp_t(v, 1));
+  v = fmax(v, dpp_t(v, 2));
+  return v;
+}
+
 }  // namespace mrcqr

@@ -12,67 +12,83 @@ namespace mrcqr {
 constexpr int GR_THREADS = 256;
 constexpr int GR_PANEL = 64;
 constexpr int GR_NMAX = 128;
-constexpr int GR_LDT = GR_NMAX + 1;
-constexpr int GR_TPW = 9;  // tiles per wave: 36 upper tiles for n = 128 over 4 waves
+constexpr int GR_NB = GR_NMAX / 16;
+constexpr int GR_LDR = 66;  // column stride (doubles) of the LDS panel
 
+// Each wave owns the upper tiles of block rows I1 = w and I2 = nb-1-w
+// (9 tiles per wave for nb = 8). Per K step it loads every block column it
+// needs once (the A and B operand layouts coincide for B^T B) and issues
+// one MFMA per tile. The panel is column-major in LDS with a 66-double
+// column stride: coalesced 64-row column stores and the operand reads
+// (16 columns x 4 rows per wave) both hit distinct banks.
 __global__ __launch_bounds__(GR_THREADS) void syrk_kernel(
     const double* __restrict__ B, int m, int n, int64_t ldb, int rows_per_chunk,
     double* __restrict__ Gpart, const Ctrl* __restrict__ ctrl, int phase) {
-  __shared__ double tile[GR_PANEL * GR_LDT];
+  __shared__ double tile[2][GR_NMAX * GR_LDR];
   if (skip_launch(ctrl, P_AUTO, phase)) return;
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63, g = l >> 4, c16 = l & 15;
   const int nb = (n + 15) / 16;
-  const int ntiles = nb * (nb + 1) / 2;
-  const int ncols = 16 * nb;
   const int64_t tstart = (int64_t)blockIdx.x * rows_per_chunk;
   const int64_t tend = min((int64_t)m, tstart + rows_per_chunk);
+  const int npan = (int)((tend - tstart + GR_PANEL - 1) / GR_PANEL);
+  const int I1 = w, I2 = nb - 1 - w;
+  const bool has1 = I1 < nb && I1 <= I2, has2 = I2 > I1;
+  const int xmin = has2 ? I1 : (has1 ? I1 : nb);
 
-  int tI[GR_TPW], tJ[GR_TPW];
+  f64x4 acc1[GR_NB], acc2[GR_NB];
 #pragma unroll
-  for (int q = 0; q < GR_TPW; ++q) {
-    int tt = w + 4 * q, I = 0;
-    if (tt >= ntiles) { tI[q] = -1; tJ[q] = -1; continue; }
-    // upper tiles in row order: (0,0),(0,1),...,(0,nb-1),(1,1),...
-    while (tt >= nb - I) { tt -= nb - I; ++I; }
-    tI[q] = I; tJ[q] = I + tt;
-  }
-  f64x4 acc[GR_TPW];
-#pragma unroll
-  for (int q = 0; q < GR_TPW; ++q) acc[q] = f64x4{0, 0, 0, 0};
+  for (int J = 0; J < GR_NB; ++J) { acc1[J] = f64x4{0, 0, 0, 0}; acc2[J] = f64x4{0, 0, 0, 0}; }
 
-  for (int64_t t0 = tstart; t0 < tend; t0 += GR_PANEL) {
-    __syncthreads();
-    for (int e = tid; e < GR_PANEL * ncols; e += GR_THREADS) {
-      const int col = e / GR_PANEL, row = e % GR_PANEL;
-      const int64_t t = t0 + row;
-      tile[row * GR_LDT + col] = (t < tend && col < n) ? B[t + (int64_t)col * ldb] : 0.0;
+  constexpr int EPT = GR_PANEL * GR_NMAX / GR_THREADS;  // 32 columns per thread, one row
+  double regs[EPT];
+  auto load_panel = [&](int64_t t0) {
+    const int64_t t = t0 + l;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int col = w + 4 * e;
+      regs[e] = (t < tend && col < n) ? B[t + (int64_t)col * ldb] : 0.0;
     }
-    __syncthreads();
-#pragma unroll 4
-    for (int kk = 0; kk < GR_PANEL / 4; ++kk) {
-      const double* trow = &tile[(4 * kk + g) * GR_LDT + c16];
+  };
+  if (npan > 0) load_panel(tstart);
+  for (int p = 0; p < npan; ++p) {
+    const int buf = p & 1;
 #pragma unroll
-      for (int q = 0; q < GR_TPW; ++q) {
-        if (tI[q] < 0) break;
-        const double a = trow[16 * tI[q]];
-        const double b = trow[16 * tJ[q]];
-        acc[q] = mfma_f64(a, b, acc[q]);
+    for (int e = 0; e < EPT; ++e) tile[buf][(w + 4 * e) * GR_LDR + l] = regs[e];
+    if (p + 1 < npan) load_panel(tstart + (int64_t)(p + 1) * GR_PANEL);
+    __syncthreads();
+    const double* tb = tile[buf] + c16 * GR_LDR + g;
+#pragma unroll 2
+    for (int kk = 0; kk < GR_PANEL / 4; ++kk) {
+      const double* tk = tb + 4 * kk;
+      double op[GR_NB];
+#pragma unroll
+      for (int X = 0; X < GR_NB; ++X) op[X] = (X >= xmin && X < nb) ? tk[16 * X * GR_LDR] : 0.0;
+      const double a1 = has1 ? tk[16 * I1 * GR_LDR] : 0.0;
+      const double a2 = has2 ? tk[16 * I2 * GR_LDR] : 0.0;
+#pragma unroll
+      for (int J = 0; J < GR_NB; ++J) {
+        if (has1 && J >= I1 && J < nb) acc1[J] = mfma_f64(a1, op[J], acc1[J]);
+        if (has2 && J >= I2 && J < nb) acc2[J] = mfma_f64(a2, op[J], acc2[J]);
       }
     }
   }
   // Gpart[chunk][col][row] for the upper tiles (f64 D layout)
   double* Gp = Gpart + (int64_t)blockIdx.x * n * n;
 #pragma unroll
-  for (int q = 0; q < GR_TPW; ++q) {
-    if (tI[q] < 0) break;
+  for (int J = 0; J < GR_NB; ++J)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int row = 16 * tI[q] + d_row_f64(l, r);
-      const int col = 16 * tJ[q] + c16;
-      if (row < n && col < n) Gp[(int64_t)col * n + row] = acc[q][r];
+      const int col = 16 * J + c16;
+      if (has1 && J >= I1 && J < nb) {
+        const int row = 16 * I1 + d_row_f64(l, r);
+        if (row < n && col < n) Gp[(int64_t)col * n + row] = acc1[J][r];
+      }
+      if (has2 && J >= I2 && J < nb) {
+        const int row = 16 * I2 + d_row_f64(l, r);
+        if (row < n && col < n) Gp[(int64_t)col * n + row] = acc2[J][r];
+      }
     }
-  }
 }
 
 // G[i, j] = G[j, i] = sum over chunks of the upper partial (i <= j). One

@@ -8,8 +8,9 @@
 // M = [[est^2 + alpha^2, alpha gamma], [alpha gamma, gamma^2]],
 // alpha = w^T x. The new estimate is the square root of M's largest (for
 // sigma_max) or smallest (sigma_min) eigenvalue, (s, c) its eigenvector.
-// M is scaled by rho^2 (rho = max(est, |alpha|, |gamma|)); the smallest
-// eigenvalue is det(M) / lam_max = (est gamma)^2 / lam_max.
+// M is scaled by 2^(-2E) with 2^E the power of two just above
+// rho = max(est, |alpha|, |gamma|) (exact scaling); the smallest eigenvalue
+// is det(M) / lam_max = (est gamma)^2 / lam_max.
 #pragma once
 #include "common.hpp"
 
@@ -19,7 +20,11 @@ __device__ __forceinline__ void ice_step(double est, double alpha, double gamma,
                                          double& s, double& c, double& est_new) {
   const double rho = fmax(fmax(est, fabs(alpha)), fabs(gamma));
   if (rho == 0.0) { s = 1.0; c = 0.0; est_new = 0.0; return; }
-  const double e = est / rho, a = alpha / rho, g = gamma / rho;
+  // rho is scaled by a power of two so the division by it is exact
+  int erho;
+  (void)frexp(rho, &erho);
+  const double e = ldexp(est, -erho), a = ldexp(alpha, -erho), g = ldexp(gamma, -erho);
+  const double scale = ldexp(1.0, erho);
   const double A = e * e + a * a, B = a * g, C = g * g;
   const double hd = 0.5 * (A - C);
   const double lmax = 0.5 * (A + C) + sqrt(hd * hd + B * B);
@@ -27,16 +32,11 @@ __device__ __forceinline__ void ice_step(double est, double alpha, double gamma,
   const double v1a = lam - C, v1b = B, v2a = B, v2b = lam - A;
   const double n1 = v1a * v1a + v1b * v1b, n2 = v2a * v2a + v2b * v2b;
   if (n1 == 0.0 && n2 == 0.0) { s = largest ? 0.0 : 1.0; c = largest ? 1.0 : 0.0; }
-  else if (n1 >= n2) { const double nn = sqrt(n1); s = v1a / nn; c = v1b / nn; }
-  else { const double nn = sqrt(n2); s = v2a / nn; c = v2b / nn; }
-  est_new = sqrt(fmax(lam, 0.0)) * rho;
+  else if (n1 >= n2) { const double r = 1.0 / sqrt(n1); s = v1a * r; c = v1b * r; }
+  else { const double r = 1.0 / sqrt(n2); s = v2a * r; c = v2b * r; }
+  est_new = sqrt(fmax(lam, 0.0)) * scale;
 }
 
-__device__ __forceinline__ double wave_sum_f64(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
 
 // kappa estimate est_max / est_min of R (element (i, j) at R[i*si + j*sj]),
 // executed by one full wave; n <= 64 * XPL. Returns +inf for a singular or
@@ -55,8 +55,8 @@ __device__ double ice_kappa_wave(const double* R, int n, int si, int sj) {
       const int i = l + 64 * q;
       if (i < j) { const double r = R[i * si + j * sj]; aM += r * xM[q]; am += r * xm[q]; }
     }
-    aM = wave_sum_f64(aM);
-    am = wave_sum_f64(am);
+    aM = wave_sum_dpp(aM);
+    am = wave_sum_dpp(am);
     const double gma = R[j * si + j * sj];
     double sM, cM, sm, cm;
     ice_step(estM, aM, gma, true, sM, cM, estM);

@@ -12,11 +12,13 @@
 // Partial sums per row chunk are reduced in a second kernel in fixed order.
 //
 // Coefficients: the phase (2t+1)k mod 4m is tracked in exact integer
-// arithmetic; FP32/FP64 sketches evaluate every coefficient from its phase
-// (quadrant reduction + Taylor polynomials on [0, pi/4]); FP16/BF16 evaluate
-// one coefficient per run of 8 consecutive rows and rotate by the angle of
-// one row step (7 rotations, error ~1e-6, far below the 2^-11 / 2^-8 unit
-// roundoff of the target format).
+// arithmetic and evaluated (quadrant reduction + Taylor polynomials on
+// [0, pi/4], float64) only to seed rotation recurrences: FP16/BF16 rotate in
+// float32 along runs of 8 consecutive rows and advance the run base by one
+// panel per panel, re-seeding exactly every 8 panels (error ~2e-6, far below
+// the 2^-11 / 2^-8 unit roundoff of the target format); FP32/FP64 rotate in
+// float64 along the lane's stride-4 row sequence and re-seed every 4 panels
+// (64 rotations, error ~1e-14).
 #include "common.hpp"
 
 namespace mrcqr {
@@ -101,7 +103,7 @@ __global__ __launch_bounds__(SK_THREADS) void sketch_kernel(
 
   __shared__ __attribute__((aligned(16))) elem tile[2][SK_NBLK * LD];
   __shared__ float esc[2][SK_NBLK];
-  __shared__ int sgn[2][SK_PANEL];
+  __shared__ uint64_t sgnm[2];
 
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63, g = l >> 4, c16 = l & 15;
@@ -115,28 +117,33 @@ __global__ __launch_bounds__(SK_THREADS) void sketch_kernel(
   const uint64_t key0 = stream_key(seed, 0);
 
   // ---- this lane's two sketch rows (one per M tile) and their phases ----
-  uint32_t kk[2], phi[2], inc_k[2], inc_p[2];
+  // phi[mt]: exact phase (2t+1)k mod 4m at the lane's first row of the
+  // current panel (t0 + 8g for the K=32 forms, t0 + g for the K=4 forms).
+  uint32_t phi[2], inc_p[2];
   bool kvalid[2];
-  float cd[2], sd[2];
+  // rotation state: (cb, sb) = cos/sin at the lane's first row of the panel
+  typedef typename std::conditional<KSTEP == 32, float, double>::type rot_t;
+  rot_t cb[2], sb[2];       // current base
+  rot_t c1[2], s1[2];       // rotation by one row step of the lane's sequence
+  rot_t cK[2], sK[2];       // rotation by 32 rows (K=32 forms only)
+  rot_t cP[2], sP[2];       // rotation by one panel (64 rows)
+  const double inv_md = 1.0 / (double)m;
 #pragma unroll
   for (int mt = 0; mt < 2; ++mt) {
     const int row = sbase + 16 * mt + c16;
     kvalid[mt] = row < s;
     const uint32_t k = kvalid[mt] ? (uint32_t)S[row] : 0u;
-    kk[mt] = k;
-    // lane's first row in a panel: t0 + 8g (K=32 forms) or t0 + g (K=4 forms)
     const uint64_t tl = (uint64_t)tstart + (KSTEP == 32 ? 8 * g : g);
     phi[mt] = phase_of(tl, k, m4);
-    inc_k[mt] = (uint32_t)((2ull * KSTEP * k) % m4);        // one K step
-    inc_p[mt] = (uint32_t)((2ull * SK_PANEL * k) % m4);     // one panel
-    if constexpr (KSTEP == 32) {
-      float c, sn;
-      phase_sincos<float>((uint32_t)((2ull * k) % m4), um, 1.0f / (float)m, c, sn);
-      cd[mt] = c; sd[mt] = sn;
-    }
+    inc_p[mt] = (uint32_t)((2ull * SK_PANEL * k) % m4);
+    // the lane steps 1 row (K=32: 8 consecutive rows) or 4 rows (K=4) at a time
+    const uint32_t step = (uint32_t)((2ull * (KSTEP == 32 ? 1 : 4) * k) % m4);
+    double c, sn;
+    phase_sincos<double>(step, um, inv_md, c, sn); c1[mt] = (rot_t)c; s1[mt] = (rot_t)sn;
+    phase_sincos<double>((uint32_t)((64ull * k) % m4), um, inv_md, c, sn); cK[mt] = (rot_t)c; sK[mt] = (rot_t)sn;
+    phase_sincos<double>(inc_p[mt], um, inv_md, c, sn); cP[mt] = (rot_t)c; sP[mt] = (rot_t)sn;
+    phase_sincos<double>(phi[mt], um, inv_md, c, sn); cb[mt] = (rot_t)c; sb[mt] = (rot_t)sn;
   }
-  const float inv_mf = 1.0f / (float)m;
-  const double inv_md = 1.0 / (double)m;
 
   // ---- accumulators ----
   typedef typename std::conditional<LOWP, f32x4, f64x4>::type accv;
@@ -162,10 +169,13 @@ __global__ __launch_bounds__(SK_THREADS) void sketch_kernel(
       }
     }
   };
+  // Rademacher signs of the panel's 64 rows as one ballot mask (bit i = row t0+i)
   auto signs_for = [&](int64_t t0, int buf) {
     if (w == 0) {
       const int64_t t = t0 + l;
-      sgn[buf][l] = (t < tend) ? (int)(hash_at(key0, (uint64_t)t) >> 63) : 0;
+      const bool neg = (t < tend) && (hash_at(key0, (uint64_t)t) >> 63);
+      const uint64_t msk = __ballot(neg);
+      if (l == 0) sgnm[buf] = msk;
     }
   };
 
@@ -179,6 +189,7 @@ __global__ __launch_bounds__(SK_THREADS) void sketch_kernel(
     const int buf = p & 1;
     const int64_t t0 = tstart + (int64_t)p * SK_PANEL;
     // 1. sign, prescale, cast, store to LDS
+    const uint32_t smask = (uint32_t)(sgnm[buf] >> lrow) & 0xFFu;
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
       const int cl = w * 16 + r * 8 + (l >> 3);
@@ -192,17 +203,15 @@ __global__ __launch_bounds__(SK_THREADS) void sketch_kernel(
 #pragma unroll
         for (int i = 0; i < 8; ++i) bad |= !isfinite(regs[r * 8 + i]);
         mx = bad ? __builtin_inf() : mx;
-        mx = fmax(mx, __shfl_xor(mx, 1));
-        mx = fmax(mx, __shfl_xor(mx, 2));
-        mx = fmax(mx, __shfl_xor(mx, 4));
+        mx = group8_max_dpp(mx);
         e = block_exp(mx);
         if ((l & 7) == 0) esc[buf][cl] = ldexpf(1.0f, -e);
       }
       elem* dst = &tile[buf][cl * LD + lrow];
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
-        double v = regs[r * 8 + i];
-        if (sgn[buf][lrow + i]) v = -v;
+        const double x = regs[r * 8 + i];
+        const double v = __hiloint2double(__double2hiint(x) ^ (int)(((smask >> i) & 1u) << 31), __double2loint(x));
         if constexpr (LOWP) {
           const float f = (float)ldexp(v, e);
           dst[i] = (elem)f;
@@ -218,63 +227,77 @@ __global__ __launch_bounds__(SK_THREADS) void sketch_kernel(
     }
     __syncthreads();
 
+    // exact re-seed of the rotation bases every 8 panels (K=32 forms, float)
+    // or every 4 panels (K=4 forms, double)
+    if (p > 0 && (p & (KSTEP == 32 ? 7 : 3)) == 0) {
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) {
+        double c, sn;
+        phase_sincos<double>(phi[mt], um, inv_md, c, sn);
+        cb[mt] = (rot_t)c; sb[mt] = (rot_t)sn;
+      }
+    }
+
     // 3. contraction of this panel
     const elem* tb = tile[buf];
+    if constexpr (KSTEP == 32) {
+      typedef typename std::conditional<P == P_FP16, half8, bf16x8>::type vec8;
 #pragma unroll
-    for (int ks = 0; ks < NKS; ++ks) {
-      if constexpr (KSTEP == 32) {
-        typedef typename std::conditional<P == P_FP16, half8, bf16x8>::type vec8;
+      for (int ks = 0; ks < NKS; ++ks) {
         vec8 bop[8];
 #pragma unroll
         for (int nt = 0; nt < 8; ++nt)
           bop[nt] = *reinterpret_cast<const vec8*>(&tb[(16 * nt + c16) * LD + KSTEP * ks + 8 * g]);
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt) {
-          float c, sn;
-          phase_sincos<float>(phi[mt], um, inv_mf, c, sn);
+          // run of 8 consecutive rows starting 32*ks rows after the base
+          float c = cb[mt], sn = sb[mt];
+          if (ks == 1) { const float cn = c * cK[mt] - sn * sK[mt]; sn = sn * cK[mt] + c * sK[mt]; c = cn; }
           vec8 aop;
 #pragma unroll
           for (int j = 0; j < 8; ++j) {
-            aop[j] = kvalid[mt] ? (typename SkT<P>::elem)c : (typename SkT<P>::elem)0.0f;
-            const float cn = c * cd[mt] - sn * sd[mt];
-            const float snn = sn * cd[mt] + c * sd[mt];
-            c = cn; sn = snn;
+            aop[j] = kvalid[mt] ? (elem)c : (elem)0.0f;
+            const float cn = c * c1[mt] - sn * s1[mt];
+            sn = sn * c1[mt] + c * s1[mt];
+            c = cn;
           }
 #pragma unroll
           for (int nt = 0; nt < 8; ++nt) {
             if constexpr (P == P_FP16) accp[mt][nt] = mfma_f16(aop, bop[nt], accp[mt][nt]);
             else accp[mt][nt] = mfma_bf16(aop, bop[nt], accp[mt][nt]);
           }
-          phi[mt] = add_mod(phi[mt], inc_k[mt], m4);
         }
-      } else {
+      }
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) {
+        const float cn = cb[mt] * cP[mt] - sb[mt] * sP[mt];
+        sb[mt] = sb[mt] * cP[mt] + cb[mt] * sP[mt];
+        cb[mt] = cn;
+      }
+    } else {
+      // the lane's rows t0 + g + 4 ks: one rotation by 4 rows per K step; after
+      // 16 steps the base sits at the next panel's first row
+#pragma unroll
+      for (int ks = 0; ks < NKS; ++ks) {
         elem bop[8];
 #pragma unroll
         for (int nt = 0; nt < 8; ++nt) bop[nt] = tb[(16 * nt + c16) * LD + KSTEP * ks + g];
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt) {
-          elem a;
-          if constexpr (P == P_FP32) {
-            float c, sn;
-            phase_sincos<float>(phi[mt], um, inv_mf, c, sn);
-            a = kvalid[mt] ? c : 0.0f;
-          } else {
-            double c, sn;
-            phase_sincos<double>(phi[mt], um, inv_md, c, sn);
-            a = kvalid[mt] ? c : 0.0;
-          }
+          const elem a = kvalid[mt] ? (elem)cb[mt] : (elem)0.0;
 #pragma unroll
           for (int nt = 0; nt < 8; ++nt) {
             if constexpr (P == P_FP32) accp[mt][nt] = mfma_f32(a, bop[nt], accp[mt][nt]);
             else acc[mt][nt] = mfma_f64(a, bop[nt], acc[mt][nt]);
           }
-          phi[mt] = add_mod(phi[mt], inc_k[mt], m4);
+          const double cn = cb[mt] * c1[mt] - sb[mt] * s1[mt];
+          sb[mt] = sb[mt] * c1[mt] + cb[mt] * s1[mt];
+          cb[mt] = cn;
         }
       }
     }
-    // phases: NKS steps of inc_k advanced one panel minus nothing; the panel
-    // step equals NKS * inc_k (mod 4m), so phi is already at the next panel.
-    (void)inc_p;
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) phi[mt] = add_mod(phi[mt], inc_p[mt], m4);
     if constexpr (LOWP) {
       // undo the block prescale of this panel (one power of two per column)
 #pragma unroll

@@ -22,43 +22,43 @@ namespace mrcqr {
 constexpr int QR_THREADS = 1024;
 
 template <typename T>
-__device__ __forceinline__ T group_sum(T v, int tpc) {
-  for (int o = tpc >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o);
-  return v;
-}
+__device__ __forceinline__ T group_sum(T v, int tpc) { return group_sum_dpp(v, tpc); }
 
 template <typename T, int RB, int NT>
 __global__ __launch_bounds__(NT) void householder_kernel(
     const double* __restrict__ Y, int s, int n, int64_t ldy, int tpc,
     double* __restrict__ Rs, int64_t ldr, double* __restrict__ kappa_out,
-    Ctrl* __restrict__ ctrl, int slot, int phase) {
+    Ctrl* __restrict__ ctrl, int slot, int phase, int want_kappa) {
   if (skip_launch(ctrl, slot, phase)) return;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int vlen = tpc * RB;
   double* Rl = reinterpret_cast<double*>(smem);          // n * n, column-major
-  T* vbuf = reinterpret_cast<T*>(Rl + (size_t)n * n);    // 2 * tpc * RB
-  T* taus = vbuf + 2 * tpc * RB;                         // 2
+  T* vbuf = reinterpret_cast<T*>(Rl + (size_t)n * n);    // 2 * vlen
+  T* taus = vbuf + 2 * vlen;                             // 2
   float* dsign = reinterpret_cast<float*>(taus + 2);     // n
   __shared__ int bad_flag;
+  __shared__ double wmax[NT / 64];
 
+  // thread -> column c, contiguous row block [rb*RB, rb*RB + RB)
   const int tid = threadIdx.x;
   const int c = tid / tpc, rb = tid % tpc;
   const bool active = c < n;
+  const int r0 = rb * RB;
   T y[RB];
 #pragma unroll
   for (int i = 0; i < RB; ++i) {
-    const int r = rb + tpc * i;
+    const int r = r0 + i;
     y[i] = (active && r < s) ? (T)Y[r + (int64_t)c * ldy] : (T)0;
   }
   if (tid == 0) bad_flag = 0;
 
   // Exact power-of-two prescale so that squares stay in range: Y * 2^es has
   // max magnitude in [0.5, 1); R is scaled back by 2^-es at the end.
-  __shared__ double wmax[NT / 64];
   {
     double lm = 0.0;
 #pragma unroll
     for (int i = 0; i < RB; ++i) lm = fmax(lm, fabs((double)y[i]));
-#pragma unroll
+    // wave max via the group sum machinery is not needed: use LDS per wave
     for (int o = 32; o > 0; o >>= 1) lm = fmax(lm, __shfl_xor(lm, o));
     if ((tid & 63) == 0) wmax[tid >> 6] = lm;
   }
@@ -72,68 +72,68 @@ __global__ __launch_bounds__(NT) void householder_kernel(
 #pragma unroll
   for (int i = 0; i < RB; ++i) y[i] = (T)ldexp((double)y[i], es);
 
-  // Branch-free column loop: the reflector buffer has tpc * RB entries
-  // (zero for rows >= s and rows < j), so every thread runs the same
-  // straight-line code over its RB rows.
-  const int vlen = tpc * RB;
+  // Reflector of column j, formed by the tpc threads that own it (LAPACK
+  // larfg convention); v is zero above row j and below row s.
+  auto reflector = [&](int j, int buf) {
+    T alpha_l = (T)0, sp[4] = {(T)0, (T)0, (T)0, (T)0};
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+      const int r = r0 + i;
+      alpha_l = (r == j) ? y[i] : alpha_l;
+      sp[i & 3] += (r > j) ? y[i] * y[i] : (T)0;
+    }
+    const T alpha = group_sum(alpha_l, tpc);
+    const T sig = group_sum((sp[0] + sp[1]) + (sp[2] + sp[3]), tpc);
+    T tau, beta, scal;
+    if (sig == (T)0) { tau = (T)0; beta = alpha; scal = (T)0; }
+    else {
+      const T nrm = sqrt(alpha * alpha + sig);
+      beta = signbit(alpha) ? nrm : -nrm;
+      tau = (beta - alpha) / beta;
+      scal = (T)1 / (alpha - beta);
+    }
+    T* v = vbuf + buf * vlen + r0;
+#pragma unroll
+    for (int i = 0; i < RB; ++i) {
+      const int r = r0 + i;
+      v[i] = (r > j) ? y[i] * scal : (r == j ? (T)1 : (T)0);
+      y[i] = (r == j) ? beta : y[i];
+    }
+    if (rb == 0) taus[buf] = tau;
+  };
+
+  if (c == 0) reflector(0, 0);
+  __syncthreads();
   for (int j = 0; j < n; ++j) {
     const int buf = j & 1;
-    T* v = vbuf + buf * vlen;
-    if (c == j) {
-      T alpha_l = (T)0, sp[4] = {(T)0, (T)0, (T)0, (T)0};
-#pragma unroll
-      for (int i = 0; i < RB; ++i) {
-        const int r = rb + tpc * i;
-        alpha_l = (r == j) ? y[i] : alpha_l;
-        sp[i & 3] += (r > j) ? y[i] * y[i] : (T)0;
-      }
-      const T alpha = group_sum(alpha_l, tpc);  // only the lane holding row j contributes
-      const T sig = group_sum((sp[0] + sp[1]) + (sp[2] + sp[3]), tpc);
-      T tau, beta, scal;
-      if (sig == (T)0) { tau = (T)0; beta = alpha; scal = (T)0; }
-      else {
-        const T nrm = sqrt(alpha * alpha + sig);
-        beta = signbit(alpha) ? nrm : -nrm;
-        tau = (beta - alpha) / beta;
-        scal = (T)1 / (alpha - beta);
-      }
-#pragma unroll
-      for (int i = 0; i < RB; ++i) {
-        const int r = rb + tpc * i;
-        v[r] = (r > j) ? y[i] * scal : (r == j ? (T)1 : (T)0);
-        y[i] = (r == j) ? beta : y[i];
-      }
-      if (rb == 0) taus[buf] = tau;
-    }
-    __syncthreads();
     if (active && c > j) {
       const T tau = taus[buf];
-      T vv[RB];
-#pragma unroll
-      for (int i = 0; i < RB; ++i) vv[i] = v[rb + tpc * i];
+      const T* v = vbuf + buf * vlen + r0;
       T dp[4] = {(T)0, (T)0, (T)0, (T)0};
 #pragma unroll
-      for (int i = 0; i < RB; ++i) dp[i & 3] += vv[i] * y[i];
+      for (int i = 0; i < RB; ++i) dp[i & 3] += v[i] * y[i];
       const T d = group_sum((dp[0] + dp[1]) + (dp[2] + dp[3]), tpc);
       const T f = tau * d;
 #pragma unroll
-      for (int i = 0; i < RB; ++i) y[i] -= f * vv[i];
+      for (int i = 0; i < RB; ++i) y[i] -= f * v[i];
+      // look-ahead: the owners of column j+1 form its reflector now, while
+      // the other columns are still being updated
+      if (c == j + 1) reflector(j + 1, buf ^ 1);
     }
+    __syncthreads();
   }
 
   // diag(R) >= 0: flip rows with a negative pivot; widen to float64.
   if (active) {
 #pragma unroll
-    for (int i = 0; i < RB; ++i) {
-      const int r = rb + tpc * i;
-      if (r == c) dsign[c] = (y[i] < (T)0) ? -1.0f : 1.0f;
-    }
+    for (int i = 0; i < RB; ++i)
+      if (r0 + i == c) dsign[c] = (y[i] < (T)0) ? -1.0f : 1.0f;
   }
   __syncthreads();
   if (active) {
 #pragma unroll
     for (int i = 0; i < RB; ++i) {
-      const int r = rb + tpc * i;
+      const int r = r0 + i;
       if (r < n) {
         const double val = (r <= c) ? ldexp((double)y[i] * (double)dsign[r], -es) : 0.0;
         Rs[r + (int64_t)c * ldr] = val;
@@ -144,8 +144,12 @@ __global__ __launch_bounds__(NT) void householder_kernel(
     }
   }
   __syncthreads();
+  const bool auto_here = ctrl != nullptr && ctrl->auto_mode;
   if (tid < 64) {
-    double kappa = bad_flag ? __builtin_inf() : ice_kappa(Rl, n, 1, n);
+    // the condition estimate drives AUTO; forced precisions skip it unless asked
+    double kappa = __builtin_nan("");
+    if (bad_flag) kappa = __builtin_inf();
+    else if (auto_here || want_kappa) kappa = ice_kappa(Rl, n, 1, n);
     if (tid == 0) {
       if (kappa_out) *kappa_out = kappa;
       if (ctrl) {
@@ -206,7 +210,7 @@ static hipError_t launch_qr_rb(const double* Y, int s, int n, int64_t ldy, doubl
   const size_t sm = qr_smem_bytes(qr_tpc(n, NT) * RB, n, sizeof(T) == 8);
   allow_dynamic_lds(reinterpret_cast<const void*>(&householder_kernel<T, RB, NT>), sm);
   hipLaunchKernelGGL((householder_kernel<T, RB, NT>), dim3(1), dim3(NT), sm, st,
-                     Y, s, n, ldy, qr_tpc(n, NT), Rs, ldr, kappa, ctrl, slot, phase);
+                     Y, s, n, ldy, qr_tpc(n, NT), Rs, ldr, kappa, ctrl, slot, phase, kappa != nullptr ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -220,6 +224,8 @@ static hipError_t launch_qr_t(const double* Y, int s, int n, int64_t ldy, double
   if (need1 <= 4) return launch_qr_rb<T, 4, 1024>(Y, s, n, ldy, Rs, ldr, kappa, ctrl, slot, phase, st);
   if (need1 <= 8) return launch_qr_rb<T, 8, 1024>(Y, s, n, ldy, Rs, ldr, kappa, ctrl, slot, phase, st);
   if (need1 <= 16) return launch_qr_rb<T, 16, 1024>(Y, s, n, ldy, Rs, ldr, kappa, ctrl, slot, phase, st);
+  if constexpr (sizeof(T) == 4)  // float fits 32 rows per thread at 1024 threads without spills
+    if (need1 <= 32) return launch_qr_rb<T, 32, 1024>(Y, s, n, ldy, Rs, ldr, kappa, ctrl, slot, phase, st);
   const int t5 = qr_tpc(n, 512);
   const int need5 = (s + t5 - 1) / t5;
   if (need5 <= 32) return launch_qr_rb<T, 32, 512>(Y, s, n, ldy, Rs, ldr, kappa, ctrl, slot, phase, st);
