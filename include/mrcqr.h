@@ -28,8 +28,10 @@
  *     after synchronizing the stream;
  *   - results are deterministic: the same inputs, seed and device give
  *     bitwise-identical outputs (no floating-point atomics).
- * Limits of this build: 1 <= n <= 128, n <= s <= m, s * n <= 65536,
- * m < 2^28.
+ * Limits of this build: 1 <= n <= 128, n <= s <= m, m < 2^28, and the
+ * sketch must fit the one-workgroup Householder QR: s <= 2048 for n <= 16,
+ * s <= 1024 for n <= 32, s <= 512 for n <= 64, s <= 256 for n <= 128
+ * (the default s = 2n always fits).
  */
 #ifndef MRCQR_H
 #define MRCQR_H

@@ -10,25 +10,31 @@
 
 namespace mrcqr {
 
-constexpr int CH_THREADS = 512;
+constexpr int CH_THREADS = 1024;
 constexpr int CH_NMAX = 128;
+constexpr int TRMM_NMAX = 128;
 
 // Right-looking Cholesky of the upper triangle of G (n <= 128), register
-// resident: thread (ty, tx) owns L[i][k] for rows i = ty + 8a (a < 16) and
-// columns k = tx + 64b (b < 2). At step j the owners of row j publish it
-// (already updated by steps < j) in LDS; every thread then updates its
-// trailing entries L[i][k] -= L[j][i] L[j][k] / piv_j. One barrier per step;
-// the rows are scaled by 1/sqrt(piv) at the end, which gives the textbook
+// resident: thread (ty, tx) owns L[i][k] for rows i = ty + 16a (a < 8) and
+// columns k = tx + 64b (b < 2). Row j, updated by steps < j, sits in LDS
+// (double-buffered); at step j every thread applies
+// L[i][k] -= L[j][i] L[j][k] / piv_j to all its entries, without a mask
+// (the update is uniform work; rows i <= j hold garbage afterwards), and
+// the owners of row j + 1 publish it and copy it to Rl, where the final
+// rows collect. One barrier per step. The rows are scaled by 1/sqrt(piv)
+// at the end, which gives the textbook
 // R[j][k] = (G[j][k] - sum_i R[i][j] R[i][k]) / R[j][j].
 __global__ __launch_bounds__(CH_THREADS) void chol_kernel(
     const double* __restrict__ G, int n, int64_t ldg, double* __restrict__ Rc, int64_t ldr,
     int32_t* __restrict__ fail_out, double* __restrict__ kappa_out, Ctrl* __restrict__ ctrl, int phase) {
   if (skip_launch(ctrl, P_AUTO, phase)) return;
-  constexpr int TY = CH_THREADS / 64;   // 8 row groups
-  constexpr int NA = CH_NMAX / TY;      // 16 rows per thread
+  constexpr int TY = CH_THREADS / 64;   // 16 row groups
+  constexpr int NA = CH_NMAX / TY;      // 8 rows per thread
   constexpr int NBK = CH_NMAX / 64;     // 2 columns per thread
+  constexpr int LDR = CH_NMAX + 1;
   __shared__ double prow[2][CH_NMAX];   // published pivot rows (double-buffered)
-  __shared__ double Rl[CH_NMAX * (CH_NMAX + 1)];
+  __shared__ double Rl[CH_NMAX * LDR];  // row-major
+  __shared__ double rscale[CH_NMAX];
   const int tid = threadIdx.x;
   const int tx = tid & 63, ty = tid >> 6;
   double Lr[NA][NBK];
@@ -39,58 +45,70 @@ __global__ __launch_bounds__(CH_THREADS) void chol_kernel(
       const int i = ty + TY * a, k = tx + 64 * b;
       Lr[a][b] = (i < n && k < n && i <= k) ? G[i + (int64_t)k * ldg] : 0.0;
     }
+  if (ty == 0) {
+#pragma unroll
+    for (int b = 0; b < NBK; ++b) {
+      prow[0][tx + 64 * b] = Lr[0][b];
+      Rl[tx + 64 * b] = Lr[0][b];
+    }
+  }
+  __syncthreads();
+  const int tyu = __builtin_amdgcn_readfirstlane(ty);
   int f = -1;
   for (int j = 0; j < n; ++j) {
     const int buf = j & 1;
-    if (ty == (j % TY)) {
-      const int aj = j / TY;
-#pragma unroll
-      for (int a = 0; a < NA; ++a)
-        if (a == aj) {
-#pragma unroll
-          for (int b = 0; b < NBK; ++b) prow[buf][tx + 64 * b] = Lr[a][b];
-        }
-    }
-    __syncthreads();
     const double piv = prow[buf][j];
+    double ri[NA], pk[NBK];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) ri[a] = prow[buf][tyu + TY * a];
+#pragma unroll
+    for (int b = 0; b < NBK; ++b) pk[b] = prow[buf][tx + 64 * b];
     if (!(piv > 0.0) || !isfinite(piv)) { f = j; break; }
-    const double inv = 1.0 / piv;
-    double rk[NBK], ri[NA];
+    const double inv = rcp_nr(piv);
+    double rk[NBK];
 #pragma unroll
-    for (int b = 0; b < NBK; ++b) rk[b] = prow[buf][tx + 64 * b] * inv;
-#pragma unroll
-    for (int a = 0; a < NA; ++a) ri[a] = prow[buf][min(ty + TY * a, CH_NMAX - 1)];
+    for (int b = 0; b < NBK; ++b) rk[b] = pk[b] * inv;
 #pragma unroll
     for (int a = 0; a < NA; ++a)
 #pragma unroll
-      for (int b = 0; b < NBK; ++b) {
-        const int i = ty + TY * a, k = tx + 64 * b;
-        const bool upd = (i > j) && (k >= i);
-        Lr[a][b] = upd ? fma(-ri[a], rk[b], Lr[a][b]) : Lr[a][b];
-      }
+      for (int b = 0; b < NBK; ++b) Lr[a][b] = fma(-ri[a], rk[b], Lr[a][b]);
+    const int jn = j + 1;
+    if (jn < n && tyu == jn % TY) {
+      const int an = jn / TY;
+#pragma unroll
+      for (int a = 0; a < NA; ++a)
+        if (a == an) {
+#pragma unroll
+          for (int b = 0; b < NBK; ++b) {
+            prow[buf ^ 1][tx + 64 * b] = Lr[a][b];
+            Rl[jn * LDR + tx + 64 * b] = Lr[a][b];
+          }
+        }
+    }
+    __syncthreads();
   }
-  // rows j < (f < 0 ? n : f) hold G's Schur rows; scale them into R
+  // rows i < nrows = (f < 0 ? n : f) of Rl hold the Schur rows; zero the
+  // strict lower triangle and the rows past a breakdown, scale row i by
+  // 1/sqrt(piv_i) (diagonal: sqrt(piv_i))
   const int nrows = (f < 0) ? n : f;
   __syncthreads();
-#pragma unroll
-  for (int a = 0; a < NA; ++a)
-#pragma unroll
-    for (int b = 0; b < NBK; ++b) {
-      const int i = ty + TY * a, k = tx + 64 * b;
-      if (i < n && k < n) Rl[i * (CH_NMAX + 1) + k] = (i <= k && i < nrows) ? Lr[a][b] : 0.0;
-    }
+  if (tid < n) {
+    const double d = Rl[tid * LDR + tid];
+    rscale[tid] = (tid < nrows) ? 1.0 / sqrt(d) : 0.0;
+  }
   __syncthreads();
-  for (int i = ty; i < nrows; i += TY) {
-    const double d = Rl[i * (CH_NMAX + 1) + i];
-    const double rinv = 1.0 / sqrt(d);
-    for (int k = i + tx; k < n; k += 64) Rl[i * (CH_NMAX + 1) + k] = (k == i) ? sqrt(d) : Rl[i * (CH_NMAX + 1) + k] * rinv;
+  for (int e = tid; e < n * n; e += CH_THREADS) {
+    const int i = e / n, k = e % n;
+    double v = 0.0;
+    if (i < nrows && k >= i) v = (k == i) ? sqrt(Rl[i * LDR + i]) : Rl[i * LDR + k] * rscale[i];
+    Rl[i * LDR + k] = v;
   }
   __syncthreads();
   for (int k = tx; k < n; k += 64)
-    for (int i = ty; i < n; i += TY) Rc[i + (int64_t)k * ldr] = (f < 0 && i <= k) ? Rl[i * (CH_NMAX + 1) + k] : 0.0;
-  if (tid < 64) {
-    double kappa = __builtin_inf();
-    if (f < 0) kappa = ice_kappa(Rl, n, CH_NMAX + 1, 1);
+    for (int i = ty; i < n; i += TY) Rc[i + (int64_t)k * ldr] = (f < 0) ? Rl[i * LDR + k] : 0.0;
+  {
+    double kappa = ice_kappa_block(Rl, n, LDR, 1, f < 0);
+    if (f >= 0) kappa = __builtin_inf();
     if (tid == 0) {
       if (fail_out) *fail_out = f;
       if (kappa_out) *kappa_out = kappa;
@@ -114,23 +132,40 @@ __global__ __launch_bounds__(CH_THREADS) void chol_kernel(
   }
 }
 
-// R = R2 R1 (upper x upper): one block per column k; column k of R1 is
-// staged in LDS and thread i forms sum_{j=i..k} R2[i][j] R1[j][k] in index
-// order (coalesced reads of R2 across threads).
-__global__ __launch_bounds__(256) void trmm_kernel(const double* __restrict__ R2, int64_t ld2,
-                                                   const double* __restrict__ R1, int64_t ld1, int n,
-                                                   double* __restrict__ R, int64_t ldr,
-                                                   const Ctrl* __restrict__ ctrl, int phase) {
+// R = R2 R1 (upper x upper), each entry sum_{j=i..k} R2[i][j] R1[j][k]
+// accumulated in index order.
+__global__ __launch_bounds__(64) void trmm_kernel(const double* __restrict__ R2, int64_t ld2,
+                                                  const double* __restrict__ R1, int64_t ld1, int n,
+                                                  double* __restrict__ R, int64_t ldr,
+                                                  const Ctrl* __restrict__ ctrl, int phase) {
+  // one wave per (64-row block, 16-column block): lane l accumulates row
+  // i = 64 blockIdx.y + l of the 16 columns c0..c0+15; R1's column slice
+  // sits in LDS, R2 is read one coalesced column at a time
+  __shared__ double r1s[TRMM_NMAX * 16];
   if (skip_launch(ctrl, P_AUTO, phase)) return;
-  extern __shared__ double col[];
-  const int k = blockIdx.x;
-  for (int j = threadIdx.x; j <= k; j += blockDim.x) col[j] = R1[j + (int64_t)k * ld1];
+  const int l = threadIdx.x;
+  const int c0 = 16 * blockIdx.x, i0 = 64 * blockIdx.y;
+  const int i = i0 + l;
+  const int jend = min(n, c0 + 16);  // R1[j][c] = 0 for j > c
+  for (int e = l; e < jend * 16; e += 64) {
+    const int j = e / 16, c = e % 16;
+    r1s[e] = (c0 + c < n && j <= c0 + c) ? R1[j + (int64_t)(c0 + c) * ld1] : 0.0;
+  }
   __syncthreads();
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    double acc = 0.0;
-    if (i <= k)
-      for (int j = i; j <= k; ++j) acc = fma(R2[i + (int64_t)j * ld2], col[j], acc);
-    R[i + (int64_t)k * ldr] = acc;
+  double acc[16];
+#pragma unroll
+  for (int c = 0; c < 16; ++c) acc[c] = 0.0;
+  // R2[i][j] = 0 for j < i: start at the block's first row
+#pragma unroll 4
+  for (int j = i0; j < jend; ++j) {
+    const double a = (i < n && j >= i) ? R2[i + (int64_t)j * ld2] : 0.0;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) acc[c] = fma(a, r1s[j * 16 + c], acc[c]);
+  }
+  if (i < n) {
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+      if (c0 + c < n) R[i + (int64_t)(c0 + c) * ldr] = acc[c];
   }
 }
 
@@ -174,9 +209,9 @@ hipError_t launch_cholesky(const double* G, int n, int64_t ldg, double* Rc, int6
 
 hipError_t launch_trmm(const double* R2, int64_t ld2, const double* R1, int64_t ld1, int n, double* R,
                        int64_t ldr, const Ctrl* ctrl, int phase, hipStream_t st) {
-  allow_dynamic_lds(reinterpret_cast<const void*>(&trmm_kernel), (size_t)n * 8);
-  hipLaunchKernelGGL(trmm_kernel, dim3(n), dim3(n < 256 ? ((n + 63) / 64) * 64 : 256), (size_t)n * 8, st, R2, ld2,
-                     R1, ld1, n, R, ldr, ctrl, phase);
+  if (n > TRMM_NMAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(trmm_kernel, dim3((n + 15) / 16, (n + 63) / 64), dim3(64), 0, st, R2, ld2, R1, ld1, n, R, ldr,
+                     ctrl, phase);
   return hipGetLastError();
 }
 

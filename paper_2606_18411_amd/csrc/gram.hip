@@ -1,52 +1,71 @@
 // Algorithm 1, first step, in float64: the Gram matrix G = B^T B of the
 // preconditioned m x n matrix. Only the upper 16 x 16 tiles are formed
-// (symmetric rank-k update). Grid = row chunks; a workgroup of 4 waves
-// stages 64-row panels of B in LDS (row-major, coalesced column loads) and
-// each wave accumulates its share of the upper tiles with float64 MFMA
+// (symmetric rank-k update). Grid = row chunks; a workgroup of 8 waves
+// (2 per SIMD) stages 64-row panels of B in LDS (coalesced column loads)
+// and each wave accumulates its share of the upper tiles with float64 MFMA
 // 16x16x4. Per-chunk partials are summed in a second kernel in fixed order
 // (deterministic, no atomics).
 #include "common.hpp"
 
 namespace mrcqr {
 
-constexpr int GR_THREADS = 256;
+constexpr int GR_THREADS = 512;
 constexpr int GR_PANEL = 64;
 constexpr int GR_NMAX = 128;
 constexpr int GR_NB = GR_NMAX / 16;
 constexpr int GR_LDR = 66;  // column stride (doubles) of the LDS panel
+constexpr int GR_TPW = 5;   // upper tiles per wave (at most)
 
-// Each wave owns the upper tiles of block rows I1 = w and I2 = nb-1-w
-// (9 tiles per wave for nb = 8). Per K step it loads every block column it
-// needs once (the A and B operand layouts coincide for B^T B) and issues
-// one MFMA per tile. The panel is column-major in LDS with a 66-double
-// column stride: coalesced 64-row column stores and the operand reads
-// (16 columns x 4 rows per wave) both hit distinct banks.
+// Upper tile u of wave w (8 waves, 8 x 8 tile grid, 36 tiles): waves 0-3
+// take tiles (p, p..p+4) of block row p = w; waves 4-7 take the rest of
+// block row p = w - 4, (p, p+5..7), and block row 7 - p, (7-p, 7-p..7).
+// Waves w and w + 4 share a SIMD and hold 9 tiles together. Tiles beyond
+// the block count nb are skipped.
+__device__ __forceinline__ void gr_tile(int w, int u, int& I, int& J) {
+  if (w < 4) { I = w; J = w + u; return; }
+  const int p = w - 4, r1 = 3 - p;  // tiles left in block row p
+  if (u < r1) { I = p; J = p + 5 + u; }
+  else if (u - r1 <= p) { I = 7 - p; J = 7 - p + (u - r1); }
+  else { I = GR_NB; J = GR_NB; }  // no tile
+}
+
+// The panel is column-major in LDS with a 66-double column stride:
+// coalesced 64-row column stores and the operand reads (16 columns x 4 rows
+// per wave) both hit distinct banks. Per K step (4 rows) a wave reads the A
+// operand of each of its block rows once and one B operand per tile, and
+// issues one float64 MFMA 16x16x4 per tile.
 __global__ __launch_bounds__(GR_THREADS) void syrk_kernel(
     const double* __restrict__ B, int m, int n, int64_t ldb, int rows_per_chunk,
     double* __restrict__ Gpart, const Ctrl* __restrict__ ctrl, int phase) {
   __shared__ double tile[2][GR_NMAX * GR_LDR];
   if (skip_launch(ctrl, P_AUTO, phase)) return;
   const int tid = threadIdx.x;
-  const int w = tid >> 6, l = tid & 63, g = l >> 4, c16 = l & 15;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63, g = l >> 4, c16 = l & 15;
   const int nb = (n + 15) / 16;
   const int64_t tstart = (int64_t)blockIdx.x * rows_per_chunk;
   const int64_t tend = min((int64_t)m, tstart + rows_per_chunk);
   const int npan = (int)((tend - tstart + GR_PANEL - 1) / GR_PANEL);
-  const int I1 = w, I2 = nb - 1 - w;
-  const bool has1 = I1 < nb && I1 <= I2, has2 = I2 > I1;
-  const int xmin = has2 ? I1 : (has1 ? I1 : nb);
 
-  f64x4 acc1[GR_NB], acc2[GR_NB];
+  int ti[GR_TPW], tj[GR_TPW];
+  bool has[GR_TPW];
 #pragma unroll
-  for (int J = 0; J < GR_NB; ++J) { acc1[J] = f64x4{0, 0, 0, 0}; acc2[J] = f64x4{0, 0, 0, 0}; }
+  for (int u = 0; u < GR_TPW; ++u) {
+    gr_tile(w, u, ti[u], tj[u]);
+    has[u] = ti[u] < nb && tj[u] < nb;
+    if (!has[u]) { ti[u] = 0; tj[u] = 0; }
+  }
+  f64x4 acc[GR_TPW];
+#pragma unroll
+  for (int u = 0; u < GR_TPW; ++u) acc[u] = f64x4{0, 0, 0, 0};
 
-  constexpr int EPT = GR_PANEL * GR_NMAX / GR_THREADS;  // 32 columns per thread, one row
+  constexpr int EPT = GR_PANEL * GR_NMAX / GR_THREADS;  // 16 columns per thread, one row
+  constexpr int CST = GR_THREADS / 64;                  // column stride of a thread's columns
   double regs[EPT];
   auto load_panel = [&](int64_t t0) {
     const int64_t t = t0 + l;
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
-      const int col = w + 4 * e;
+      const int col = w + CST * e;
       regs[e] = (t < tend && col < n) ? B[t + (int64_t)col * ldb] : 0.0;
     }
   };
@@ -54,41 +73,42 @@ __global__ __launch_bounds__(GR_THREADS) void syrk_kernel(
   for (int p = 0; p < npan; ++p) {
     const int buf = p & 1;
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) tile[buf][(w + 4 * e) * GR_LDR + l] = regs[e];
+    for (int e = 0; e < EPT; ++e) tile[buf][(w + CST * e) * GR_LDR + l] = regs[e];
     if (p + 1 < npan) load_panel(tstart + (int64_t)(p + 1) * GR_PANEL);
     __syncthreads();
     const double* tb = tile[buf] + c16 * GR_LDR + g;
 #pragma unroll 2
     for (int kk = 0; kk < GR_PANEL / 4; ++kk) {
       const double* tk = tb + 4 * kk;
-      double op[GR_NB];
+      if (w < 4) {
+        // one block row: one A operand, B operands of blocks p..p+4
+        const double a = tk[16 * ti[0] * GR_LDR];
 #pragma unroll
-      for (int X = 0; X < GR_NB; ++X) op[X] = (X >= xmin && X < nb) ? tk[16 * X * GR_LDR] : 0.0;
-      const double a1 = has1 ? tk[16 * I1 * GR_LDR] : 0.0;
-      const double a2 = has2 ? tk[16 * I2 * GR_LDR] : 0.0;
+        for (int u = 0; u < GR_TPW; ++u) {
+          const double bo = (u == 0) ? a : tk[16 * tj[u] * GR_LDR];
+          if (has[u]) acc[u] = mfma_f64(a, bo, acc[u]);
+        }
+      } else {
 #pragma unroll
-      for (int J = 0; J < GR_NB; ++J) {
-        if (has1 && J >= I1 && J < nb) acc1[J] = mfma_f64(a1, op[J], acc1[J]);
-        if (has2 && J >= I2 && J < nb) acc2[J] = mfma_f64(a2, op[J], acc2[J]);
+        for (int u = 0; u < GR_TPW - 1; ++u) {
+          const double a = tk[16 * ti[u] * GR_LDR];
+          const double bo = tk[16 * tj[u] * GR_LDR];
+          if (has[u]) acc[u] = mfma_f64(a, bo, acc[u]);
+        }
       }
     }
   }
   // Gpart[chunk][col][row] for the upper tiles (f64 D layout)
   double* Gp = Gpart + (int64_t)blockIdx.x * n * n;
 #pragma unroll
-  for (int J = 0; J < GR_NB; ++J)
+  for (int u = 0; u < GR_TPW; ++u) {
+    if (!has[u]) continue;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int col = 16 * J + c16;
-      if (has1 && J >= I1 && J < nb) {
-        const int row = 16 * I1 + d_row_f64(l, r);
-        if (row < n && col < n) Gp[(int64_t)col * n + row] = acc1[J][r];
-      }
-      if (has2 && J >= I2 && J < nb) {
-        const int row = 16 * I2 + d_row_f64(l, r);
-        if (row < n && col < n) Gp[(int64_t)col * n + row] = acc2[J][r];
-      }
+      const int col = 16 * tj[u] + c16, row = 16 * ti[u] + d_row_f64(l, r);
+      if (row < n && col < n) Gp[(int64_t)col * n + row] = acc[u][r];
     }
+  }
 }
 
 // G[i, j] = G[j, i] = sum over chunks of the upper partial (i <= j). One
@@ -134,7 +154,7 @@ struct GramGeom { int chunks, rows_per_chunk; };
 
 GramGeom gram_geometry(int64_t m) {
   const int64_t npan = (m + GR_PANEL - 1) / GR_PANEL;
-  const int64_t target = 512;
+  const int64_t target = 256;  // one workgroup per compute unit
   const int64_t per = (npan + target - 1) / target;
   GramGeom gg;
   gg.rows_per_chunk = (int)(per * GR_PANEL);

@@ -63,7 +63,9 @@ def test_sketch_rows_and_columns_are_independent(M):
 
 @pytest.mark.parametrize("qrp", ["fp64", "fp32"])
 @pytest.mark.parametrize("s,n,kappa", [(64, 32, 1e3), (256, 128, 1e3), (48, 20, 1e2), (16, 8, 10.0),
-                                       (130, 100, 1e2), (256, 128, 1e8)])
+                                       (130, 100, 1e2), (256, 128, 1e8), (100, 50, 1e4), (200, 64, 1e6),
+                                       (300, 40, 1e2), (512, 64, 1e3), (250, 128, 1e4), (1024, 32, 1e3),
+                                       (2048, 16, 1e5), (1, 1, 1.0)])
 def test_sketch_qr_matches_householder(M, qrp, s, n, kappa):
     if qrp == "fp32" and kappa > 1e6:
         pytest.skip("float32 QR of a kappa=1e8 matrix is outside its accuracy range")
@@ -140,7 +142,7 @@ def test_cholesky_breakdown_index(M, j):
     assert np.all(to_host(Rc) == 0)
 
 
-@pytest.mark.parametrize("n", [1, 7, 64, 128])
+@pytest.mark.parametrize("n", [1, 7, 64, 100, 128])
 def test_trmm_matches_product(M, n):
     R2 = W.upper_triangular(n, 10.0, 9)
     R1 = W.upper_triangular(n, 1e5, 10)
