@@ -110,13 +110,16 @@ def main() -> int:
     for _ in range(3):
         M.trsm(A, Rs, X, workspace=tws)
     torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    for e0, e1 in evs:
-        e0.record(stream)
+    # back-to-back launches between two events on the library's stream; one
+    # launch = the R staging kernel (a few us) + trsm_kernel
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
         M.trsm(A, Rs, X, workspace=tws)
-        e1.record(stream)
+    e1.record(stream)
     torch.cuda.synchronize()
-    trsm_ms = float(np.mean([e0.elapsed_time(e1) for e0, e1 in evs]))
+    trsm_ms = e0.elapsed_time(e1) / args.steps
     trsm_bytes = 2.0 * 8.0 * m * n  # read A, write X (algorithmic)
     achieved = trsm_bytes / (trsm_ms * 1e-3) / 1e9
     log(f"trsm kernel: {trsm_ms:.4f} ms/launch, {achieved:.1f} GB/s")

@@ -63,10 +63,16 @@ __global__ __launch_bounds__(GR_THREADS) void syrk_kernel(
   double regs[EPT];
   auto load_panel = [&](int64_t t0) {
     const int64_t t = t0 + l;
+    if (t0 + GR_PANEL <= tend && n == GR_NMAX) {
+      const double* bp = B + t + (int64_t)w * ldb;
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      const int col = w + CST * e;
-      regs[e] = (t < tend && col < n) ? B[t + (int64_t)col * ldb] : 0.0;
+      for (int e = 0; e < EPT; ++e) regs[e] = bp[(int64_t)(CST * e) * ldb];
+    } else {
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const int col = w + CST * e;
+        regs[e] = (t < tend && col < n) ? B[t + (int64_t)col * ldb] : 0.0;
+      }
     }
   };
   if (npan > 0) load_panel(tstart);
@@ -77,24 +83,32 @@ __global__ __launch_bounds__(GR_THREADS) void syrk_kernel(
     if (p + 1 < npan) load_panel(tstart + (int64_t)(p + 1) * GR_PANEL);
     __syncthreads();
     const double* tb = tile[buf] + c16 * GR_LDR + g;
-#pragma unroll 2
-    for (int kk = 0; kk < GR_PANEL / 4; ++kk) {
-      const double* tk = tb + 4 * kk;
-      if (w < 4) {
-        // one block row: one A operand, B operands of blocks p..p+4
+    // no branches in the K loop: a tile that does not exist (beyond nb)
+    // reads block 0 and its accumulator is never stored
+    if (w < 4) {
+      // one block row: one A operand, B operands of blocks p..p+4
+#pragma unroll 4
+      for (int kk = 0; kk < GR_PANEL / 4; ++kk) {
+        const double* tk = tb + 4 * kk;
+        double bo[GR_TPW];
+#pragma unroll
+        for (int u = 0; u < GR_TPW; ++u) bo[u] = tk[16 * tj[u] * GR_LDR];
         const double a = tk[16 * ti[0] * GR_LDR];
 #pragma unroll
-        for (int u = 0; u < GR_TPW; ++u) {
-          const double bo = (u == 0) ? a : tk[16 * tj[u] * GR_LDR];
-          if (has[u]) acc[u] = mfma_f64(a, bo, acc[u]);
-        }
-      } else {
+        for (int u = 0; u < GR_TPW; ++u) acc[u] = mfma_f64(a, bo[u], acc[u]);
+      }
+    } else {
+#pragma unroll 4
+      for (int kk = 0; kk < GR_PANEL / 4; ++kk) {
+        const double* tk = tb + 4 * kk;
+        double ao[GR_TPW - 1], bo[GR_TPW - 1];
 #pragma unroll
         for (int u = 0; u < GR_TPW - 1; ++u) {
-          const double a = tk[16 * ti[u] * GR_LDR];
-          const double bo = tk[16 * tj[u] * GR_LDR];
-          if (has[u]) acc[u] = mfma_f64(a, bo, acc[u]);
+          ao[u] = tk[16 * ti[u] * GR_LDR];
+          bo[u] = tk[16 * tj[u] * GR_LDR];
         }
+#pragma unroll
+        for (int u = 0; u < GR_TPW - 1; ++u) acc[u] = mfma_f64(ao[u], bo[u], acc[u]);
       }
     }
   }
