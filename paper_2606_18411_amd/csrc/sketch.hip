@@ -86,6 +86,23 @@ __device__ __forceinline__ int block_exp(double mu) {
   return e < -100 ? -100 : (e > 100 ? 100 : e);
 }
 
+// The same exponent from the largest biased exponent field F of a block:
+// mu = 0.1xx..b * 2^(F - 1022) for normal mu gives e = 15 - (F - 1022);
+// F = 0 (zeros or subnormals) gives the clamp 100 (all-zero blocks give
+// zero values whatever e is); F = 0x7FF (inf, NaN) gives 0.
+__device__ __forceinline__ int block_exp_field(uint32_t F) {
+  if (F == 0x7FFu) return 0;
+  const int e = 1037 - (int)F;
+  return e < -100 ? -100 : (e > 100 ? 100 : e);
+}
+
+__device__ __forceinline__ uint32_t group8_max_u32_dpp(uint32_t v) {
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false));
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false));
+  return v;
+}
+
 template <int P>
 __global__ __launch_bounds__(SK_THREADS) void sketch_kernel(
     const double* __restrict__ A, int64_t lda, int m, int n,
@@ -127,6 +144,7 @@ __global__ __launch_bounds__(SK_THREADS) void sketch_kernel(
   rot_t c1[2], s1[2];       // rotation by one row step of the lane's sequence
   rot_t cK[2], sK[2];       // rotation by 32 rows (K=32 forms only)
   rot_t cP[2], sP[2];       // rotation by one panel (64 rows)
+  float tc1[2];             // 2 cos(one row step), K=32 forms
   const double inv_md = 1.0 / (double)m;
 #pragma unroll
   for (int mt = 0; mt < 2; ++mt) {
@@ -140,6 +158,7 @@ __global__ __launch_bounds__(SK_THREADS) void sketch_kernel(
     const uint32_t step = (uint32_t)((2ull * (KSTEP == 32 ? 1 : 4) * k) % m4);
     double c, sn;
     phase_sincos<double>(step, um, inv_md, c, sn); c1[mt] = (rot_t)c; s1[mt] = (rot_t)sn;
+    tc1[mt] = (float)(2.0 * c);
     phase_sincos<double>((uint32_t)((64ull * k) % m4), um, inv_md, c, sn); cK[mt] = (rot_t)c; sK[mt] = (rot_t)sn;
     phase_sincos<double>(inc_p[mt], um, inv_md, c, sn); cP[mt] = (rot_t)c; sP[mt] = (rot_t)sn;
     phase_sincos<double>(phi[mt], um, inv_md, c, sn); cb[mt] = (rot_t)c; sb[mt] = (rot_t)sn;
@@ -159,13 +178,22 @@ __global__ __launch_bounds__(SK_THREADS) void sketch_kernel(
   double regs[16];
   const int lrow = 8 * (l & 7);
   auto load_panel = [&](int64_t t0) {
+    if (t0 + SK_PANEL <= tend && cbase + SK_NBLK <= n) {
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const int col = cbase + w * 16 + r * 8 + (l >> 3);
+      for (int r = 0; r < 2; ++r) {
+        const double* ap = A + t0 + lrow + (int64_t)(cbase + w * 16 + r * 8 + (l >> 3)) * lda;
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int64_t t = t0 + lrow + i;
-        regs[r * 8 + i] = (col < n && t < tend) ? A[t + (int64_t)col * lda] : 0.0;
+        for (int i = 0; i < 8; ++i) regs[r * 8 + i] = ap[i];
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const int col = cbase + w * 16 + r * 8 + (l >> 3);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          const int64_t t = t0 + lrow + i;
+          regs[r * 8 + i] = (col < n && t < tend) ? A[t + (int64_t)col * lda] : 0.0;
+        }
       }
     }
   };
@@ -195,16 +223,13 @@ __global__ __launch_bounds__(SK_THREADS) void sketch_kernel(
       const int cl = w * 16 + r * 8 + (l >> 3);
       int e = 0;
       if constexpr (LOWP) {
-        double mx = 0.0;
+        // the largest biased exponent field of the block decides e (the
+        // element of largest magnitude has it); 0x7FF = inf or NaN
+        uint32_t fm = 0;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) mx = fmax(mx, fabs(regs[r * 8 + i]));
-        // propagate a NaN so the whole block keeps it (fmax drops NaN)
-        bool bad = false;
-#pragma unroll
-        for (int i = 0; i < 8; ++i) bad |= !isfinite(regs[r * 8 + i]);
-        mx = bad ? __builtin_inf() : mx;
-        mx = group8_max_dpp(mx);
-        e = block_exp(mx);
+        for (int i = 0; i < 8; ++i) fm = max(fm, ((uint32_t)__double2hiint(regs[r * 8 + i]) >> 20) & 0x7FFu);
+        fm = group8_max_u32_dpp(fm);
+        e = block_exp_field(fm);
         if ((l & 7) == 0) esc[buf][cl] = ldexpf(1.0f, -e);
       }
       elem* dst = &tile[buf][cl * LD + lrow];
@@ -213,7 +238,10 @@ __global__ __launch_bounds__(SK_THREADS) void sketch_kernel(
         const double x = regs[r * 8 + i];
         const double v = __hiloint2double(__double2hiint(x) ^ (int)(((smask >> i) & 1u) << 31), __double2loint(x));
         if constexpr (LOWP) {
-          const float f = (float)ldexp(v, e);
+          // two roundings, float64 -> float32 -> p (the barrier keeps the
+          // compiler from fusing them into one float64 -> p conversion)
+          float f = (float)ldexp(v, e);
+          asm volatile("" : "+v"(f));
           dst[i] = (elem)f;
         } else {
           dst[i] = v;
@@ -250,21 +278,28 @@ __global__ __launch_bounds__(SK_THREADS) void sketch_kernel(
           bop[nt] = *reinterpret_cast<const vec8*>(&tb[(16 * nt + c16) * LD + KSTEP * ks + 8 * g]);
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt) {
-          // run of 8 consecutive rows starting 32*ks rows after the base
+          // run of 8 consecutive rows starting 32*ks rows after the base:
+          // first two values by rotation, the rest by the three-term
+          // recurrence cos((t+1)w) = 2 cos(w) cos(tw) - cos((t-1)w). Rows
+          // of sketch rows >= s are computed too and never stored.
           float c = cb[mt], sn = sb[mt];
           if (ks == 1) { const float cn = c * cK[mt] - sn * sK[mt]; sn = sn * cK[mt] + c * sK[mt]; c = cn; }
           vec8 aop;
+          float cprev = c, ccur = c * c1[mt] - sn * s1[mt];
+          aop[0] = (elem)cprev;
+          aop[1] = (elem)ccur;
 #pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            aop[j] = kvalid[mt] ? (elem)c : (elem)0.0f;
-            const float cn = c * c1[mt] - sn * s1[mt];
-            sn = sn * c1[mt] + c * s1[mt];
-            c = cn;
+          for (int j = 2; j < 8; ++j) {
+            const float cn = fmaf(tc1[mt], ccur, -cprev);
+            cprev = ccur;
+            ccur = cn;
+            aop[j] = (elem)ccur;
           }
 #pragma unroll
           for (int nt = 0; nt < 8; ++nt) {
-            if constexpr (P == P_FP16) accp[mt][nt] = mfma_f16(aop, bop[nt], accp[mt][nt]);
-            else accp[mt][nt] = mfma_bf16(aop, bop[nt], accp[mt][nt]);
+            const accv cin = (ks == 0) ? accv{0, 0, 0, 0} : accp[mt][nt];
+            if constexpr (P == P_FP16) accp[mt][nt] = mfma_f16(aop, bop[nt], cin);
+            else accp[mt][nt] = mfma_bf16(aop, bop[nt], cin);
           }
         }
       }
@@ -307,7 +342,7 @@ __global__ __launch_bounds__(SK_THREADS) void sketch_kernel(
         for (int mt = 0; mt < 2; ++mt) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) acc[mt][nt][r] = fmaf(accp[mt][nt][r], sc, acc[mt][nt][r]);
-          accp[mt][nt] = accv{0, 0, 0, 0};
+          if constexpr (KSTEP != 32) accp[mt][nt] = accv{0, 0, 0, 0};
         }
       }
     }
