@@ -31,6 +31,26 @@ METRIC = "ms/QR at m=2^20,n=128: FP16-sketch vs FP64-sketch at â€–Iâˆ’Qáµ€Qâ€–â‰
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
+# HBM traffic of one trsm_kernel<128> launch at m = 2^20, n = 128 from two
+# rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of
+# this script with --copy-calibration, each scaled by what the counter reads
+# for the 256 MiB device copy of that run (FETCH_SIZE reads half the copied
+# bytes, WRITE_SIZE all of them); profiles/trsm_kernel_traffic_m1048576_n128.md
+# holds the numbers. Reported only while the kernel source is the one the
+# counters were taken on.
+TRSM_TRAFFIC = {"fetch_kib": 525400.0, "fetch_factor": 2.0, "write_kib": 1049000.0, "write_factor": 1.0,
+                "source_sha256": "091e39b443ec6f82b3e60e3df5fb122f6e9a376bbf671d3dc88fd2da64c2cedb"}
+
+
+def trsm_traffic_bytes():
+    import hashlib
+    src = os.path.join(ROOT, "paper_2606_18411_amd", "csrc", "trsm.hip")
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != TRSM_TRAFFIC["source_sha256"]:
+            return None
+    t = TRSM_TRAFFIC
+    return 1024.0 * (t["fetch_kib"] * t["fetch_factor"] + t["write_kib"] * t["write_factor"])
+
 
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -45,7 +65,9 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--kappa", type=float, default=1e4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-rows", type=int, default=1 << 18)
+    ap.add_argument("--cpu-sample-rows", type=int, default=1 << 20)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 256 MiB device copy first (reference for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the factorization of one matrix "
@@ -58,6 +80,13 @@ def main() -> int:
 
     M.lib()
     m, n, kappa = args.m, args.n, args.kappa
+    if args.copy_calibration:
+        src = torch.ones(32 << 20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     s = 2 * n
     torch.cuda.set_device(0)
     log(f"generating A: m={m} n={n} kappa={kappa:g}")
@@ -163,7 +192,10 @@ def main() -> int:
         "accuracy": acc,
         "roofline": {"kernel": "trsm_kernel<128> (X = A R^-1, float64)", "bound": "hbm",
                      "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": (round(trsm_traffic_bytes() / 1e9, 4) if (m, n) == (1 << 20, 128) and
+                                 trsm_traffic_bytes() is not None else None),
+                     "traffic_unit": "GB per launch", "algorithmic_bytes_per_launch": trsm_bytes,
                      "ms_per_launch": round(trsm_ms, 5)},
         "cpu_baseline": cpu,
     }

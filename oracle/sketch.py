@@ -50,8 +50,11 @@ def signed_cast(A: np.ndarray, d: np.ndarray, prec: int) -> np.ndarray:
     return P.cast_blockscaled(at, prec)
 
 
-def sketch(A: np.ndarray, S: np.ndarray, d: np.ndarray, prec: int, chunk: int = 1 << 15) -> np.ndarray:
-    """Y (s x n) per the definition above; float64 array (FP32-valued unless FP64)."""
+def sketch(A: np.ndarray, S: np.ndarray, d: np.ndarray, prec: int, chunk: int = 1 << 15,
+           s_total: int | None = None) -> np.ndarray:
+    """Y (s x n) per the definition above; float64 array (FP32-valued unless FP64).
+    s_total: the sketch size the gammas refer to when S holds only some of
+    the sampled rows (default: len(S))."""
     A = np.asarray(A, dtype=np.float64)
     m, n = A.shape
     S = np.asarray(S, dtype=np.int64)
@@ -64,13 +67,14 @@ def sketch(A: np.ndarray, S: np.ndarray, d: np.ndarray, prec: int, chunk: int = 
         if prec != P.FP64:
             c = P.round_to(c, prec)
         y += c @ at[t0:t0 + t.shape[0]]
-    y *= gammas(S, s)[:, None]
+    y *= gammas(S, s if s_total is None else s_total)[:, None]
     if prec != P.FP64:
         y = P.to_f32(y)
     return y
 
 
-def sketch_abs_bound(A: np.ndarray, S: np.ndarray, d: np.ndarray, prec: int, chunk: int = 1 << 15) -> np.ndarray:
+def sketch_abs_bound(A: np.ndarray, S: np.ndarray, d: np.ndarray, prec: int, chunk: int = 1 << 15,
+                     s_total: int | None = None) -> np.ndarray:
     """gamma_k * sum_t |c(k,t)| |at[t,j]|: the scale against which rounding
     errors of the sketch are measured (elementwise)."""
     A = np.asarray(A, dtype=np.float64)
@@ -81,4 +85,4 @@ def sketch_abs_bound(A: np.ndarray, S: np.ndarray, d: np.ndarray, prec: int, chu
     for t0 in range(0, m, chunk):
         t = np.arange(t0, min(m, t0 + chunk), dtype=np.int64)
         y += np.abs(coefficients(S, t, m)) @ at[t0:t0 + t.shape[0]]
-    return y * gammas(S, S.shape[0])[:, None]
+    return y * gammas(S, S.shape[0] if s_total is None else s_total)[:, None]

@@ -6,8 +6,12 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle import householder as HH, metrics as MT
+from oracle import householder as HH, metrics as MT, precision as P, rng, sketch as SK
 from gpu_common import require_gpu, to_dev, to_host, progress, torch
+
+U32 = 2.0 ** -24
+# same bounds as the small-size sketch parity test
+SKETCH_TOL = {P.FP64: 2e-12, P.FP16: 2e-5}
 
 pytestmark = pytest.mark.gpu
 
@@ -40,3 +44,32 @@ def test_headline_shape(M, big, prec):
     assert MT.rel_diff(Rh, Rt) <= tol
     rows = np.random.default_rng(0).choice(m, 512, replace=False)
     assert np.max(np.abs(Qh[rows] - U[rows] @ Qt)) <= tol
+
+
+@pytest.mark.parametrize("prec,name", [(P.FP16, "fp16"), (P.FP64, "fp64")])
+def test_headline_sketch_sampled_rows(M, big, prec, name):
+    """Full-size sketch in the bench's launch configuration; 3 of the s = 256
+    sampled rows (first, middle, last) against the oracle, elementwise."""
+    A = big[0]
+    m, n = A.shape
+    s, seed = 2 * n, 5
+    progress(f"full size sketch {name}")
+    S = rng.sample_rows(seed, m, s)
+    assert np.array_equal(to_host(M.draw(seed, m, s)), S)
+    Y = to_host(M.sketch(to_dev(A), torch.from_numpy(S.astype(np.int32)).cuda(), seed, name))
+    pick = np.array([0, s // 2, s - 1])
+    d = rng.signs(seed, m)
+    Yo = SK.sketch(A, S[pick], d, prec, s_total=s)
+    bound = SK.sketch_abs_bound(A, S[pick], d, prec, s_total=s)
+    tol = SKETCH_TOL[prec] * bound + (U32 * np.abs(Yo) if prec != P.FP64 else 0)
+    assert np.all(np.abs(Y[pick] - Yo) <= tol)
+
+
+def test_headline_shape_auto(M, big):
+    A, U, Qt, Rt, kappa = big
+    progress("full size auto")
+    Q, R, info = M.factor(to_dev(A), "auto", seed=4)
+    assert info.status == 0, info
+    Qh, Rh = to_host(Q), to_host(R)
+    assert MT.orthogonality(Qh) <= 1e-13
+    assert MT.residual(A, Qh, Rh, 1.0) <= 1e-13
