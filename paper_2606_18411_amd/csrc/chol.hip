@@ -139,26 +139,50 @@ __global__ __launch_bounds__(64) void trmm_kernel(const double* __restrict__ R2,
                                                   double* __restrict__ R, int64_t ldr,
                                                   const Ctrl* __restrict__ ctrl, int phase) {
   // one wave per (64-row block, 16-column block): lane l accumulates row
-  // i = 64 blockIdx.y + l of the 16 columns c0..c0+15; R1's column slice
-  // sits in LDS, R2 is read one coalesced column at a time
+  // i = 64 blockIdx.y + l of the 16 columns c0..c0+15. The needed parts of
+  // R2 (rows i0..i0+63, columns i0..jend-1) and of R1 (rows 0..jend-1,
+  // the 16 columns) are staged in LDS first, with all loads in flight.
   __shared__ double r1s[TRMM_NMAX * 16];
+  __shared__ double r2s[64 * (TRMM_NMAX + 1)];
   if (skip_launch(ctrl, P_AUTO, phase)) return;
   const int l = threadIdx.x;
   const int c0 = 16 * blockIdx.x, i0 = 64 * blockIdx.y;
   const int i = i0 + l;
   const int jend = min(n, c0 + 16);  // R1[j][c] = 0 for j > c
-  for (int e = l; e < jend * 16; e += 64) {
-    const int j = e / 16, c = e % 16;
-    r1s[e] = (c0 + c < n && j <= c0 + c) ? R1[j + (int64_t)(c0 + c) * ld1] : 0.0;
+  // loads with clamped (always valid) addresses and no branches, so that
+  // they are all in flight together; the masks are applied afterwards
+  {
+    double v[32];
+#pragma unroll
+    for (int u = 0; u < 32; ++u) {
+      const int e = l + 64 * u, j = min(e / 16, n - 1), c = e % 16;
+      v[u] = R1[j + (int64_t)min(c0 + c, n - 1) * ld1];
+    }
+#pragma unroll
+    for (int u = 0; u < 32; ++u) {
+      const int e = l + 64 * u, j = e / 16, c = e % 16;
+      if (e < jend * 16) r1s[e] = (c0 + c < n && j <= c0 + c) ? v[u] : 0.0;
+    }
+  }
+  // R2[i][j] for j in [i0, jend): column j of the block is read coalesced,
+  // 16 columns in flight at a time
+  const int ic = min(i, n - 1);
+  for (int j0 = i0; j0 < jend; j0 += 16) {
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = R2[ic + (int64_t)min(j0 + u, n - 1) * ld2];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int j = j0 + u;
+      if (j < jend) r2s[l * (TRMM_NMAX + 1) + (j - i0)] = (i < n && j >= i) ? v[u] : 0.0;
+    }
   }
   __syncthreads();
   double acc[16];
 #pragma unroll
   for (int c = 0; c < 16; ++c) acc[c] = 0.0;
-  // R2[i][j] = 0 for j < i: start at the block's first row
-#pragma unroll 4
   for (int j = i0; j < jend; ++j) {
-    const double a = (i < n && j >= i) ? R2[i + (int64_t)j * ld2] : 0.0;
+    const double a = r2s[l * (TRMM_NMAX + 1) + (j - i0)];
 #pragma unroll
     for (int c = 0; c < 16; ++c) acc[c] = fma(a, r1s[j * 16 + c], acc[c]);
   }

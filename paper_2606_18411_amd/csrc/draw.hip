@@ -18,7 +18,33 @@ __device__ __forceinline__ uint32_t floyd_r(uint64_t key1, uint64_t j) {
   return (uint32_t)__umul64hi(hash_at(key1, j), j + 1);
 }
 
+// Ascending bitonic sort of keys[0..P) (P a power of two). With one key per
+// thread (P <= blockDim.x) the exchanges inside a wave are shuffles and
+// only distances >= 64 go through LDS (3 of 36 stages at P = 256).
 __device__ void bitonic_sort(uint32_t* keys, int P) {
+  if (P <= (int)blockDim.x) {
+    const int i = threadIdx.x;
+    uint32_t v = (i < P) ? keys[i] : 0xFFFFFFFFu;
+    for (int k = 2; k <= P; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        uint32_t o;
+        if (j >= 64) {
+          __syncthreads();
+          if (i < P) keys[i] = v;
+          __syncthreads();
+          o = (i < P) ? keys[i ^ j] : v;
+        } else {
+          o = (uint32_t)__shfl_xor((int)v, j);
+        }
+        const bool up = (i & k) == 0, lower = (i & j) == 0;
+        v = (lower == up) ? min(v, o) : max(v, o);
+      }
+    }
+    __syncthreads();
+    if (i < P) keys[i] = v;
+    __syncthreads();
+    return;
+  }
   for (int k = 2; k <= P; k <<= 1) {
     for (int j = k >> 1; j > 0; j >>= 1) {
       for (int i = threadIdx.x; i < P; i += blockDim.x) {
@@ -89,7 +115,10 @@ __global__ void signs_kernel(uint64_t seed, int m, int8_t* D) {
 }
 
 hipError_t launch_draw(uint64_t seed, int m, int s, int32_t* S, int8_t* D, hipStream_t st) {
-  hipLaunchKernelGGL(draw_kernel, dim3(1), dim3(DRAW_THREADS), 0, st, seed, m, s, S);
+  int P = 1;
+  while (P < s) P <<= 1;
+  const int threads = P <= DRAW_THREADS ? (P < 64 ? 64 : P) : DRAW_THREADS;
+  hipLaunchKernelGGL(draw_kernel, dim3(1), dim3(threads), 0, st, seed, m, s, S);
   if (D) {
     int blocks = (m + 255) / 256;
     if (blocks > 4096) blocks = 4096;
