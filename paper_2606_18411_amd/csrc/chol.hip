@@ -141,9 +141,10 @@ __global__ __launch_bounds__(64) void trmm_kernel(const double* __restrict__ R2,
   // one wave per (64-row block, 16-column block): lane l accumulates row
   // i = 64 blockIdx.y + l of the 16 columns c0..c0+15. The needed parts of
   // R2 (rows i0..i0+63, columns i0..jend-1) and of R1 (rows 0..jend-1,
-  // the 16 columns) are staged in LDS first, with all loads in flight.
+  // the 16 columns) are staged in LDS first. Only the upper triangles of
+  // R1 and R2 are read as values.
   __shared__ double r1s[TRMM_NMAX * 16];
-  __shared__ double r2s[64 * (TRMM_NMAX + 1)];
+  __shared__ __attribute__((aligned(16))) double r2s[64 * TRMM_NMAX];
   if (skip_launch(ctrl, P_AUTO, phase)) return;
   const int l = threadIdx.x;
   const int c0 = 16 * blockIdx.x, i0 = 64 * blockIdx.y;
@@ -164,17 +165,29 @@ __global__ __launch_bounds__(64) void trmm_kernel(const double* __restrict__ R2,
       if (e < jend * 16) r1s[e] = (c0 + c < n && j <= c0 + c) ? v[u] : 0.0;
     }
   }
-  // R2[i][j] for j in [i0, jend): column j of the block is read coalesced,
-  // 16 columns in flight at a time
-  const int ic = min(i, n - 1);
-  for (int j0 = i0; j0 < jend; j0 += 16) {
-    double v[16];
+  // R2[i][j] for j in [i0, jend), column-major in LDS (64 rows per column).
+  // A full 64-row block with an even leading dimension is copied by direct
+  // global-to-LDS loads (two columns of 16-byte pairs per instruction, all
+  // in flight together); otherwise element by element.
+  const bool direct = (i0 + 64 <= n) && ((ld2 & 1) == 0) && ((reinterpret_cast<uintptr_t>(R2) & 15) == 0);
+  if (direct) {
+    typedef __attribute__((address_space(3))) void lds_t;
+    const int ncol = jend - i0;
+    for (int k = 0; 2 * k < ncol; ++k) {
+      const int jj = min(2 * k + (l >> 5), ncol - 1);
+      const double* src = R2 + (i0 + 2 * (l & 31)) + (int64_t)(i0 + jj) * ld2;
+      __builtin_amdgcn_global_load_lds(src, (lds_t*)(r2s + 128 * k), 16, 0, 0);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+  } else {
+    const int ic = min(i, n - 1);
+    for (int j0 = i0; j0 < jend; j0 += 16) {
+      double v[16];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) v[u] = R2[ic + (int64_t)min(j0 + u, n - 1) * ld2];
+      for (int u = 0; u < 16; ++u) v[u] = R2[ic + (int64_t)min(j0 + u, n - 1) * ld2];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int j = j0 + u;
-      if (j < jend) r2s[l * (TRMM_NMAX + 1) + (j - i0)] = (i < n && j >= i) ? v[u] : 0.0;
+      for (int u = 0; u < 16; ++u)
+        if (j0 + u < jend) r2s[(j0 + u - i0) * 64 + l] = v[u];
     }
   }
   __syncthreads();
@@ -182,7 +195,7 @@ __global__ __launch_bounds__(64) void trmm_kernel(const double* __restrict__ R2,
 #pragma unroll
   for (int c = 0; c < 16; ++c) acc[c] = 0.0;
   for (int j = i0; j < jend; ++j) {
-    const double a = r2s[l * (TRMM_NMAX + 1) + (j - i0)];
+    const double a = (i < n && j >= i) ? r2s[(j - i0) * 64 + l] : 0.0;  // upper triangle of R2 only
 #pragma unroll
     for (int c = 0; c < 16; ++c) acc[c] = fma(a, r1s[j * 16 + c], acc[c]);
   }
