@@ -143,7 +143,7 @@ __global__ __launch_bounds__(64) void trmm_kernel(const double* __restrict__ R2,
   // R2 (rows i0..i0+63, columns i0..jend-1) and of R1 (rows 0..jend-1,
   // the 16 columns) are staged in LDS first. Only the upper triangles of
   // R1 and R2 are read as values.
-  __shared__ double r1s[TRMM_NMAX * 16];
+  __shared__ __attribute__((aligned(16))) double r1s[TRMM_NMAX * 16];
   __shared__ __attribute__((aligned(16))) double r2s[64 * TRMM_NMAX];
   if (skip_launch(ctrl, P_AUTO, phase)) return;
   const int l = threadIdx.x;
@@ -191,13 +191,21 @@ __global__ __launch_bounds__(64) void trmm_kernel(const double* __restrict__ R2,
     }
   }
   __syncthreads();
+  // only the upper triangle of R2 is a value: zero row i's entries j < i
+  // (all of them for rows past n), then the product loop has no branches
+  const int ncol = jend - i0;
+  const int zlim = (i < n) ? min(l, ncol) : ncol;
+  for (int jj = 0; jj < zlim; ++jj) r2s[jj * 64 + l] = 0.0;
+  __syncthreads();
   double acc[16];
 #pragma unroll
   for (int c = 0; c < 16; ++c) acc[c] = 0.0;
-  for (int j = i0; j < jend; ++j) {
-    const double a = (i < n && j >= i) ? r2s[(j - i0) * 64 + l] : 0.0;  // upper triangle of R2 only
+#pragma unroll 4
+  for (int jj = 0; jj < ncol; ++jj) {
+    const double a = r2s[jj * 64 + l];
+    const double* rr = r1s + (i0 + jj) * 16;
 #pragma unroll
-    for (int c = 0; c < 16; ++c) acc[c] = fma(a, r1s[j * 16 + c], acc[c]);
+    for (int c = 0; c < 16; ++c) acc[c] = fma(a, rr[c], acc[c]);
   }
   if (i < n) {
 #pragma unroll

@@ -162,7 +162,7 @@ hipError_t launch_trsm(const double* A, int m, int n, int64_t lda, const double*
   hipLaunchKernelGGL(trsm_prep_kernel, dim3((prep_elems + 255) / 256), dim3(256), 0, st, R, n, ldr, Rop, Dg,
                      ctrl, phase);
   const int64_t panels = ((int64_t)m + TR_ROWS - 1) / TR_ROWS;
-  const int grid = (int)(panels < 512 ? panels : 512);
+  const int grid = (int)(panels < 256 ? panels : 256);  // one workgroup per CU (LDS-bound)
   if (grid < 1) return hipGetLastError();
   if (n <= 32) hipLaunchKernelGGL(trsm_kernel<32>, dim3(grid), dim3(TR_THREADS), 0, st, A, m, n, lda, Rop, Dg, X, ldx, ctrl, phase);
   else if (n <= 64) hipLaunchKernelGGL(trsm_kernel<64>, dim3(grid), dim3(TR_THREADS), 0, st, A, m, n, lda, Rop, Dg, X, ldx, ctrl, phase);
