@@ -11,6 +11,9 @@
  *           of Y giving the preconditioner Rs;
  *   Stage 2 (float64): B = A Rs^{-1}, then Cholesky-QR of B (Algorithm 1):
  *           G = B^T B, G = Rc^T Rc, Q = B Rc^{-1};
+ *           B = A Rs^{-1} is a substitution (Rs may be as ill conditioned as
+ *           A); Q is the product of B with the explicit inverse of Rc,
+ *           whose condition number is that of B, a small constant;
  *   Stage 3: R = Rc Rs.
  *
  * Conventions for every entry point:
@@ -177,6 +180,22 @@ int mrcqr_gram(const double* B, int64_t m, int64_t n, int64_t ldb,
  * kappa_dev (may be NULL) the ICE estimate of kappa_2(Rc). */
 int mrcqr_cholesky(const double* G, int64_t n, int64_t ldg, double* Rc, int64_t ldr,
                    int32_t* fail_dev, double* kappa_dev, void* stream);
+
+/* Algorithm 1 step 3, first half: X = R^{-1} for an upper-triangular
+ * n x n R (n <= 128) by column-wise back substitution, x_i = (e_j -
+ * sum_{k>i} r_ik x_k)_i / r_ii. Only the upper triangle of R is read; the
+ * strict lower triangle of X is written as zeros. X must not overlap R. A
+ * zero or non-finite diagonal entry gives non-finite columns (no status;
+ * in the factorization the Cholesky status covers it). Meant for the
+ * well-conditioned Rc: the error of X grows like n u kappa(R). */
+int mrcqr_tri_inverse(const double* R, int64_t n, int64_t ldr, double* X, int64_t ldx, void* stream);
+
+/* Algorithm 1 step 3, second half: Q = B X for B (m x n) and an
+ * upper-triangular X (n x n, only its upper triangle is read; X = Rc^{-1}
+ * from mrcqr_tri_inverse in the factorization). Q must not overlap B. No
+ * workspace. */
+int mrcqr_form_q(const double* B, int64_t m, int64_t n, int64_t ldb, const double* X, int64_t ldx,
+                 double* Q, int64_t ldq, void* stream);
 
 /* Stage 3: R = R2 R1 for upper-triangular n x n factors. */
 int mrcqr_trmm(const double* R2, int64_t ld2, const double* R1, int64_t ld1,

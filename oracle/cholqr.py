@@ -54,6 +54,29 @@ def cholesky_upper(G: np.ndarray) -> np.ndarray:
     return R
 
 
+def upper_inverse(R: np.ndarray) -> np.ndarray:
+    """X = R^{-1} for upper-triangular R: column j solves R x = e_j by back
+    substitution, x_i = (e_j[i] - R[i, i+1:j+1] x[i+1:j+1]) / r_ii for
+    i = j, ..., 0 (rows below j are zero). Algorithm 1 forms Q = B Rc^{-1};
+    with kappa(Rc) = kappa(B) small this inverse may be applied as a
+    product (Rs, which can be ill conditioned, is only ever solved with)."""
+    R = np.asarray(R, dtype=np.float64)
+    n = R.shape[0]
+    X = np.zeros((n, n), dtype=np.float64)
+    for j in range(n):
+        x = np.zeros(j + 1)
+        for i in range(j, -1, -1):
+            rhs = (1.0 if i == j else 0.0) - R[i, i + 1:j + 1] @ x[i + 1:j + 1]
+            x[i] = rhs / R[i, i]
+        X[:j + 1, j] = x
+    return X
+
+
+def form_q(B: np.ndarray, X: np.ndarray) -> np.ndarray:
+    """Q = B X for upper-triangular X (the plain product)."""
+    return np.asarray(B, dtype=np.float64) @ np.triu(np.asarray(X, dtype=np.float64))
+
+
 def trmm_upper(R2: np.ndarray, Rs: np.ndarray) -> np.ndarray:
     """R = R2 Rs (product of upper-triangular factors, Stage 3)."""
     return np.triu(np.asarray(R2) @ np.asarray(Rs))

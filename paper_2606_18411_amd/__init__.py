@@ -65,6 +65,8 @@ def lib() -> ctypes.CDLL:
             "mrcqr_gram": (i32, [vp, i64, i64, i64, vp, i64, vp, sz, vp]),
             "mrcqr_cholesky": (i32, [vp, i64, i64, vp, i64, vp, vp, vp]),
             "mrcqr_trmm": (i32, [vp, i64, vp, i64, i64, vp, i64, vp]),
+            "mrcqr_tri_inverse": (i32, [vp, i64, i64, vp, i64, vp]),
+            "mrcqr_form_q": (i32, [vp, i64, i64, i64, vp, i64, vp, i64, vp]),
             "mrcqr_condest": (i32, [vp, i64, i64, vp, vp]),
             "mrcqr_status_string": (ctypes.c_char_p, [i32]),
             "mrcqr_version": (i32, []),
@@ -286,6 +288,23 @@ def trmm(R2: torch.Tensor, R1: torch.Tensor, stream=None) -> torch.Tensor:
     _check(lib().mrcqr_trmm(R2.data_ptr(), _ld(R2), R1.data_ptr(), _ld(R1), n, R.data_ptr(), _ld(R),
                             _stream(stream)), "mrcqr_trmm")
     return R
+
+
+def tri_inverse(R: torch.Tensor, stream=None) -> torch.Tensor:
+    n = R.shape[0]
+    X = empty_colmajor(n, n, R.device)
+    _check(lib().mrcqr_tri_inverse(R.data_ptr(), n, _ld(R), X.data_ptr(), _ld(X), _stream(stream)),
+           "mrcqr_tri_inverse")
+    return X
+
+
+def form_q(B: torch.Tensor, X: torch.Tensor, Q: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    m, n = B.shape
+    if Q is None:
+        Q = empty_colmajor(m, n, B.device)
+    _check(lib().mrcqr_form_q(B.data_ptr(), m, n, _ld(B), X.data_ptr(), _ld(X), Q.data_ptr(), _ld(Q),
+                              _stream(stream)), "mrcqr_form_q")
+    return Q
 
 
 def condest(R: torch.Tensor, stream=None) -> torch.Tensor:

@@ -27,6 +27,10 @@ hipError_t launch_cholesky(const double* G, int n, int64_t ldg, double* Rc, int6
                            double* kappa, Ctrl* ctrl, int phase, hipStream_t st);
 hipError_t launch_trmm(const double* R2, int64_t ld2, const double* R1, int64_t ld1, int n, double* R,
                        int64_t ldr, const Ctrl* ctrl, int phase, hipStream_t st);
+hipError_t launch_trinv(const double* R, int n, int64_t ldr, double* X, int64_t ldx, const Ctrl* ctrl, int phase,
+                        hipStream_t st);
+hipError_t launch_qform(const double* B, int m, int n, int64_t ldb, const double* X, int64_t ldx, double* Q,
+                        int64_t ldq, const Ctrl* ctrl, int phase, hipStream_t st);
 hipError_t launch_ctrl_init(Ctrl* ctrl, int prec, int auto_mode, hipStream_t st);
 hipError_t launch_ctrl_finalize(const Ctrl* ctrl, void* info, hipStream_t st);
 }  // namespace mrcqr
@@ -62,7 +66,7 @@ int hip_status(hipError_t e) { return e == hipSuccess ? MRCQR_OK : MRCQR_ERR_DEV
 
 struct mrcqr_plan {
   int64_t m, n, s;
-  size_t off_ctrl, off_S, off_Ypart, off_Y, off_Rs, off_Gpart, off_G, off_Rc, off_Tw, off_B, total;
+  size_t off_ctrl, off_S, off_Ypart, off_Y, off_Rs, off_Gpart, off_G, off_Rc, off_Rci, off_Tw, off_B, total;
 };
 
 static void plan_layout(mrcqr_plan* p) {
@@ -77,6 +81,7 @@ static void plan_layout(mrcqr_plan* p) {
   p->off_Gpart = take(gram_partial_bytes(p->m, p->n));
   p->off_G = take(n * n * sizeof(double));
   p->off_Rc = take(n * n * sizeof(double));
+  p->off_Rci = take(n * n * sizeof(double));
   p->off_Tw = take(trsm_workspace_bytes((int)n));
   p->off_B = take(m * n * sizeof(double));
   p->total = o;
@@ -93,6 +98,7 @@ static int execute(const mrcqr_plan* p, char* ws, const double* A, int64_t lda, 
   double* Gpart = reinterpret_cast<double*>(ws + p->off_Gpart);
   double* G = reinterpret_cast<double*>(ws + p->off_G);
   double* Rc = reinterpret_cast<double*>(ws + p->off_Rc);
+  double* Rci = reinterpret_cast<double*>(ws + p->off_Rci);
   double* B = reinterpret_cast<double*>(ws + p->off_B);
   void* Tw = ws + p->off_Tw;
   const int64_t ldb = p->m;
@@ -111,7 +117,8 @@ static int execute(const mrcqr_plan* p, char* ws, const double* A, int64_t lda, 
     return launch_trsm(A, m, n, lda, Rs, n, B, ldb, Tw, ctrl, phase, st) == hipSuccess &&
            launch_gram(B, m, n, ldb, Gpart, G, n, ctrl, phase, st) == hipSuccess &&
            launch_cholesky(G, n, n, Rc, n, nullptr, nullptr, ctrl, phase, st) == hipSuccess &&
-           launch_trsm(B, m, n, ldb, Rc, n, Q, ldq, Tw, ctrl, tail_phase, st) == hipSuccess &&
+           launch_trinv(Rc, n, n, Rci, n, ctrl, tail_phase, st) == hipSuccess &&
+           launch_qform(B, m, n, ldb, Rci, n, Q, ldq, ctrl, tail_phase, st) == hipSuccess &&
            launch_trmm(Rc, n, Rs, n, n, R, ldr, ctrl, tail_phase, st) == hipSuccess;
   };
   if (automode) {
@@ -294,6 +301,19 @@ int mrcqr_trmm(const double* R2, int64_t ld2, const double* R1, int64_t ld1, int
   if (!R2 || !R1 || !R || n < 1 || ld2 < n || ld1 < n || ldr < n) return MRCQR_ERR_ARG;
   if (n > 4096) return MRCQR_ERR_UNSUPPORTED;
   return hip_status(launch_trmm(R2, ld2, R1, ld1, (int)n, R, ldr, nullptr, PH_FIRST, as_stream(stream)));
+}
+
+int mrcqr_tri_inverse(const double* R, int64_t n, int64_t ldr, double* X, int64_t ldx, void* stream) {
+  if (!R || !X || n < 1 || ldr < n || ldx < n || R == X) return MRCQR_ERR_ARG;
+  if (n > NMAX) return MRCQR_ERR_UNSUPPORTED;
+  return hip_status(launch_trinv(R, (int)n, ldr, X, ldx, nullptr, PH_FIRST, as_stream(stream)));
+}
+
+int mrcqr_form_q(const double* B, int64_t m, int64_t n, int64_t ldb, const double* X, int64_t ldx, double* Q,
+                 int64_t ldq, void* stream) {
+  if (!B || !X || !Q || m < 1 || n < 1 || ldb < m || ldx < n || ldq < m || B == Q) return MRCQR_ERR_ARG;
+  if (n > NMAX || m >= MMAX) return MRCQR_ERR_UNSUPPORTED;
+  return hip_status(launch_qform(B, (int)m, (int)n, ldb, X, ldx, Q, ldq, nullptr, PH_FIRST, as_stream(stream)));
 }
 
 int mrcqr_condest(const double* R, int64_t n, int64_t ldr, double* kappa_dev, void* stream) {

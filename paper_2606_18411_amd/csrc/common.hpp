@@ -35,6 +35,15 @@ __device__ __forceinline__ f64x4 mfma_f64(double a, double b, f64x4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// f(integral_constant<0>), ..., f(integral_constant<N-1>), in this order
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (N > 0) {
+    static_for<N - 1>(f);
+    f(std::integral_constant<int, N - 1>{});
+  }
+}
+
 // Counter-based generator (SplitMix64 of Steele, Lea and Flood, 2014).
 //   key(seed, stream) = mix64(seed ^ stream * 0xD1B54A32D192ED03)
 //   h(key, i)         = mix64(key + (i + 1) * 0x9E3779B97F4A7C15)

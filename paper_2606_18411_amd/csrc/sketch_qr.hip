@@ -47,15 +47,6 @@ __device__ void sketch_qr_epilogue(const double* Rl, int n, bool bad, double* __
   }
 }
 
-// f(integral_constant<0>), ..., f(integral_constant<N-1>), in this order
-template <int N, typename F>
-__device__ __forceinline__ void static_for(F&& f) {
-  if constexpr (N > 0) {
-    static_for<N - 1>(f);
-    f(std::integral_constant<int, N - 1>{});
-  }
-}
-
 template <typename T>
 __device__ __forceinline__ T group_sum(T v, int tpc) { return group_sum_dpp(v, tpc); }
 

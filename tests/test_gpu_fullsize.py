@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle import householder as HH, metrics as MT, precision as P, rng, sketch as SK
+from oracle import cholqr as CQ, householder as HH, metrics as MT, precision as P, rng, sketch as SK
 from gpu_common import require_gpu, to_dev, to_host, progress, torch
 
 U32 = 2.0 ** -24
@@ -73,3 +73,22 @@ def test_headline_shape_auto(M, big):
     Qh, Rh = to_host(Q), to_host(R)
     assert MT.orthogonality(Qh) <= 1e-13
     assert MT.residual(A, Qh, Rh, 1.0) <= 1e-13
+
+
+def test_headline_solve_and_form_q_sampled_rows(M, big):
+    """B = A R^{-1} and Q = B X at the full size in the bench's launch
+    configuration; 512 sampled rows (first and last included) against the
+    oracle's substitution and product."""
+    A = big[0]
+    m, n = A.shape
+    progress("full size trsm + form_q")
+    R = W.upper_triangular(n, 1e4, 31)
+    X = W.upper_triangular(n, 30.0, 32)
+    B = M.trsm(to_dev(A), to_dev(R))
+    Q = M.form_q(B, to_dev(X))
+    rows = np.concatenate([[0, m - 1], np.random.default_rng(1).choice(np.arange(1, m - 1), 510, replace=False)])
+    ridx = torch.from_numpy(rows).cuda()
+    Bh, Qh = to_host(B[ridx]), to_host(Q[ridx])
+    Bo = CQ.trsm_right_upper(A[rows], R)
+    assert np.linalg.norm(Bh - Bo) / np.linalg.norm(Bo) <= 10 * n * 2.0 ** -53 * 1e4
+    assert np.all(np.abs(Qh - CQ.form_q(Bh, X)) <= 2 * n * 2.0 ** -53 * (np.abs(Bh) @ np.abs(X)))

@@ -142,6 +142,36 @@ def test_cholesky_breakdown_index(M, j):
     assert np.all(to_host(Rc) == 0)
 
 
+@pytest.mark.parametrize("n,kappa", [(1, 1.0), (7, 10.0), (16, 1e2), (33, 30.0), (64, 1e3), (100, 10.0),
+                                     (128, 30.0), (128, 1e4)])
+def test_tri_inverse_matches_substitution(M, n, kappa):
+    progress(f"tri_inverse n={n} kappa={kappa:g}")
+    R = W.upper_triangular(n, kappa, 20 + n)
+    Rg = R + np.tril(np.full((n, n), np.nan), -1)  # only the upper triangle may be read
+    X = to_host(M.tri_inverse(to_dev(Rg)))
+    Xo = CQ.upper_inverse(R)
+    assert np.array_equal(np.tril(X, -1), np.zeros((n, n)))
+    # componentwise forward error of a triangular inverse: ~ n u |X| |R| |X|
+    bound = np.abs(Xo) @ np.abs(R) @ np.abs(Xo)
+    assert np.all(np.abs(X - Xo) <= 8 * n * U64 * bound)
+
+
+@pytest.mark.parametrize("m,n,pad", [(1, 1, 0), (5, 3, 0), (100, 16, 0), (129, 7, 3), (1000, 33, 0),
+                                     (4096 + 37, 64, 0), (50000, 100, 0), (70001, 128, 0), (1 << 16, 128, 0),
+                                     (20000, 128, 5), (300, 48, 0)])
+def test_form_q_matches_product(M, m, n, pad):
+    progress(f"form_q m={m} n={n} pad={pad}")
+    B = W.gaussian(m, n, 12)
+    X = W.upper_triangular(n, 30.0, 13 + n)
+    Xg = X + np.tril(np.full((n, n), np.nan), -1)  # only the upper triangle may be read
+    Bd = to_dev(np.vstack([B, np.full((pad, n), np.nan)]))[:m] if pad else to_dev(B)
+    Qd = M.form_q(Bd, to_dev(Xg))
+    Q = to_host(Qd)
+    Qo = CQ.form_q(B, X)
+    # any summation order: |Q - B X| <= n u |B| |X|
+    assert np.all(np.abs(Q - Qo) <= 2 * n * U64 * (np.abs(B) @ np.abs(X)))
+
+
 @pytest.mark.parametrize("n", [1, 7, 64, 100, 128])
 def test_trmm_matches_product(M, n):
     R2 = W.upper_triangular(n, 10.0, 9)

@@ -73,6 +73,43 @@ def test_trsm_matches_scipy():
     assert np.max(np.abs(X @ R - A)) < 1e-12 * np.abs(A).max() * 20
 
 
+def test_upper_inverse_closed_forms():
+    # 2 x 2 with dyadic entries: [[a, b], [0, c]]^{-1} = [[1/a, -b/(ac)], [0, 1/c]] exactly
+    X = CQ.upper_inverse(np.array([[2.0, 3.0], [0.0, 4.0]]))
+    assert np.array_equal(X, np.array([[0.5, -0.375], [0.0, 0.25]]))
+    # unit upper bidiagonal with -1 above the diagonal: the inverse is the
+    # all-ones upper triangle (x_i = x_{i+1} for every column), exactly
+    n = 9
+    R = np.eye(n) - np.eye(n, k=1)
+    assert np.array_equal(CQ.upper_inverse(R), np.triu(np.ones((n, n))))
+    # a diagonal matrix inverts entrywise
+    d = np.array([2.0, -4.0, 0.5, 8.0])
+    assert np.array_equal(CQ.upper_inverse(np.diag(d)), np.diag(1.0 / d))
+
+
+def test_upper_inverse_matches_scipy():
+    R = W.upper_triangular(40, 1e6, 9)
+    X = CQ.upper_inverse(R)
+    ref = scipy.linalg.solve_triangular(R, np.eye(40), lower=False)
+    assert np.max(np.abs(X - ref)) <= 1e-9 * np.abs(ref).max()
+    assert np.array_equal(np.tril(X, -1), np.zeros((40, 40)))
+    assert np.max(np.abs(R @ X - np.eye(40))) <= 1e-9
+
+
+def test_form_q_is_orthogonal_with_inverse_of_cholesky_factor():
+    # Algorithm 1 with the inverse applied as a product: for a
+    # well-conditioned B the result is orthonormal to working accuracy and
+    # agrees with the substitution Q = B Rc^{-1}
+    B = W.test_matrix(4000, 24, 10.0, 11)
+    Rc = CQ.cholesky_upper(CQ.gram(B))
+    Q = CQ.form_q(B, CQ.upper_inverse(Rc))
+    assert MT.orthogonality(Q) <= 1e-14
+    assert np.max(np.abs(Q - CQ.trsm_right_upper(B, Rc))) <= 1e-14
+    # only the upper triangle of X is used
+    X = CQ.upper_inverse(Rc)
+    assert np.array_equal(CQ.form_q(B, X + np.tril(np.ones_like(X), -1)), Q)
+
+
 def test_cholesky_matches_numpy():
     G = W.spd_matrix(40, 1e6, 7)
     R = CQ.cholesky_upper(G)
