@@ -38,8 +38,8 @@ FP64_PEAK_TFLOPS = 78.6
 # bytes, WRITE_SIZE all of them); profiles/trsm_kernel_traffic_m1048576_n128.md
 # holds the numbers. Reported only while the kernel source is the one the
 # counters were taken on.
-TRSM_TRAFFIC = {"fetch_kib": 525400.0, "fetch_factor": 2.0, "write_kib": 1049000.0, "write_factor": 1.0,
-                "source_sha256": "091e39b443ec6f82b3e60e3df5fb122f6e9a376bbf671d3dc88fd2da64c2cedb"}
+TRSM_TRAFFIC = {"fetch_kib": 525300.0, "fetch_factor": 2.0, "write_kib": 1048577.0, "write_factor": 1.0,
+                "source_sha256": "5256a4636f8730afdfcc85fc6ee72852231679be39e75bf168089c09a16de1ef"}
 
 
 def trsm_traffic_bytes():
