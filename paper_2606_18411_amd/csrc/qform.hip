@@ -14,7 +14,8 @@
 // of X. The wave solves R x = e_j by back substitution
 // (x_i = (e_j - sum_{k>i} r_ik x_k)_i / r_ii for i = j..0) in column order:
 // once x_i is known, r_ki x_i is taken off the right-hand side of every
-// row k < i. Lane l holds rows l and l + 64.
+// row k < i. Lane l holds rows l and l + 64; x_i is formed on the lane
+// holding row i (with that lane's reciprocal of r_ii) and read from there.
 //
 // qform_kernel<NB>: Q = B X with X upper triangular (NB = ceil(n / 16)
 // blocks of 16 columns). X is staged once per workgroup in LDS in MFMA
@@ -37,36 +38,40 @@ constexpr int QF_CH = 4;  // K-step pairs per chunk
 
 __host__ __device__ constexpr int qf_off(int J, int q) { return 64 * (2 * J * (J + 1) + q); }
 
-__global__ __launch_bounds__(64) void trinv_kernel(const double* __restrict__ R, int n, int64_t ldr,
-                                                   double* __restrict__ X, int64_t ldx,
-                                                   const Ctrl* __restrict__ ctrl, int phase) {
+// Column solves of trinv_kernel: wave v of block b solves column j = 2 b + v.
+__global__ __launch_bounds__(128) void trinv_kernel(const double* __restrict__ R, int n, int64_t ldr,
+                                                    double* __restrict__ X, int64_t ldx,
+                                                    const Ctrl* __restrict__ ctrl, int phase) {
   if (skip_launch(ctrl, P_AUTO, phase)) return;
   constexpr int U = 8;
-  const int j = blockIdx.x, l = threadIdx.x;
+  const int j = 2 * blockIdx.x + (threadIdx.x >> 6), l = threadIdx.x & 63;
+  if (j >= n) return;
   const int ra = min(l, n - 1), rb = min(l + 64, n - 1);  // clamped: always valid addresses
+  // each lane's own rows' reciprocal diagonal: x_i is formed on the lane
+  // that holds row i and read from there
+  const double rinv0 = 1.0 / R[ra + (int64_t)ra * ldr], rinv1 = 1.0 / R[rb + (int64_t)rb * ldr];
   double s0 = (l == j) ? 1.0 : 0.0, s1 = (l + 64 == j) ? 1.0 : 0.0;
-  double pa[U], pb[U], pd[U];
+  double pa[U], pb[U];
   auto fetch = [&](int i0) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t i = max(i0 - u, 0);
       pa[u] = R[ra + i * ldr];
       pb[u] = R[rb + i * ldr];
-      pd[u] = R[i + i * ldr];
     }
   };
   fetch(j);
   for (int i0 = j; i0 >= 0; i0 -= U) {
-    double ca[U], cb[U], cd[U];
+    double ca[U], cb[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) { ca[u] = pa[u]; cb[u] = pb[u]; cd[u] = pd[u]; }
+    for (int u = 0; u < U; ++u) { ca[u] = pa[u]; cb[u] = pb[u]; }
     if (i0 - U >= 0) fetch(i0 - U);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int i = i0 - u;
       if (i < 0) break;
-      const double own = (i < 64) ? s0 : s1;
-      const double x = readlane_t(own / cd[u], i & 63);
+      const double own = (i < 64) ? s0 * rinv0 : s1 * rinv1;
+      const double x = readlane_t(own, i & 63);
       s0 = (l == i) ? x : ((l < i) ? fma(-ca[u], x, s0) : s0);
       s1 = (l + 64 == i) ? x : ((l + 64 < i) ? fma(-cb[u], x, s1) : s1);
     }
@@ -286,7 +291,7 @@ __global__ __launch_bounds__(NT == 2 ? 256 : 512) void qform_kernel(
 hipError_t launch_trinv(const double* R, int n, int64_t ldr, double* X, int64_t ldx, const Ctrl* ctrl, int phase,
                         hipStream_t st) {
   if (n > QF_NMAX) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(trinv_kernel, dim3(n), dim3(64), 0, st, R, n, ldr, X, ldx, ctrl, phase);
+  hipLaunchKernelGGL(trinv_kernel, dim3((n + 1) / 2), dim3(128), 0, st, R, n, ldr, X, ldx, ctrl, phase);
   return hipGetLastError();
 }
 

@@ -352,8 +352,8 @@ __global__ void condest_kernel(const double* __restrict__ R, int n, int64_t ldr,
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   double* Rl = reinterpret_cast<double*>(smem);
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-    const int i = e / n, j = e % n;  // row-major copy
-    Rl[e] = (i <= j) ? R[i + (int64_t)j * ldr] : 0.0;
+    const int i = e % n, j = e / n;  // coalesced reads, row-major copy
+    Rl[i * n + j] = (i <= j) ? R[i + (int64_t)j * ldr] : 0.0;
   }
   __syncthreads();
   const double k = ice_kappa_block(Rl, n, n, 1, true);
