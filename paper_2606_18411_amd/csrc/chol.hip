@@ -10,105 +10,155 @@
 
 namespace mrcqr {
 
-constexpr int CH_THREADS = 1024;
+constexpr int CH_THREADS = 512;
 constexpr int CH_NMAX = 128;
 constexpr int TRMM_NMAX = 128;
 
-// Right-looking Cholesky of the upper triangle of G (n <= 128), register
-// resident: thread (ty, tx) owns L[i][k] for rows i = ty + 16a (a < 8) and
-// columns k = tx + 64b (b < 2). Row j, updated by steps < j, sits in LDS
-// (double-buffered); at step j every thread applies
-// L[i][k] -= L[j][i] L[j][k] / piv_j to all its entries, without a mask
-// (the update is uniform work; rows i <= j hold garbage afterwards), and
-// the owners of row j + 1 publish it and copy it to Rl, where the final
-// rows collect. One barrier per step. The rows are scaled by 1/sqrt(piv)
-// at the end, which gives the textbook
-// R[j][k] = (G[j][k] - sum_i R[i][j] R[i][k]) / R[j][j].
+// Blocked right-looking Cholesky of the upper triangle of G (n <= 128),
+// 16-column blocks, all of it in LDS (row-major, stride 129). Block step K:
+//   A. wave 0 factors the 16 x 16 diagonal block: lane c holds column c of
+//      the block, and step j forms r_jj = sqrt(pivot), scales row j and
+//      takes r_ji r_jc off every entry (i, c), j < i <= c (r_ji read from
+//      lane i);
+//   B. the row panel R[K, >K] = R_KK^{-T} G[K, >K], one thread per column
+//      (forward substitution);
+//   C. the trailing upper tiles lose R[K, I]^T R[K, J] (float64 MFMA
+//      16x16x4, 16 waves).
+// Each entry ends as the textbook R[j][k] = (G[j][k] - sum_{i<j} R[i][j]
+// R[i][k]) / R[j][j], summed in another order. A pivot that is not
+// positive and finite stops the factorization (its index is reported).
 __global__ __launch_bounds__(CH_THREADS) void chol_kernel(
     const double* __restrict__ G, int n, int64_t ldg, double* __restrict__ Rc, int64_t ldr,
     int32_t* __restrict__ fail_out, double* __restrict__ kappa_out, Ctrl* __restrict__ ctrl, int phase) {
   if (skip_launch(ctrl, P_AUTO, phase)) return;
-  constexpr int TY = CH_THREADS / 64;   // 16 row groups
-  constexpr int NA = CH_NMAX / TY;      // 8 rows per thread
-  constexpr int NBK = CH_NMAX / 64;     // 2 columns per thread
   constexpr int LDR = CH_NMAX + 1;
-  __shared__ double prow[2][CH_NMAX];   // published pivot rows (double-buffered)
   __shared__ double Rl[CH_NMAX * LDR];  // row-major
-  __shared__ double rscale[CH_NMAX];
+  __shared__ double dinv[16];           // 1 / r_jj of the current diagonal block
+  __shared__ int fail_sh;
   const int tid = threadIdx.x;
-  const int tx = tid & 63, ty = tid >> 6;
-  double Lr[NA][NBK];
+  const int w = tid >> 6, l = tid & 63, g = l >> 4, c16 = l & 15;
+  // upper triangle of G, zero elsewhere (coalesced over the rows of a
+  // column; all of a thread's loads in flight together)
+  {
+    constexpr int PER = CH_NMAX * CH_NMAX / CH_THREADS;
+    double v[PER];
 #pragma unroll
-  for (int a = 0; a < NA; ++a)
-#pragma unroll
-    for (int b = 0; b < NBK; ++b) {
-      const int i = ty + TY * a, k = tx + 64 * b;
-      Lr[a][b] = (i < n && k < n && i <= k) ? G[i + (int64_t)k * ldg] : 0.0;
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + u * CH_THREADS, i = e % CH_NMAX, j = e / CH_NMAX;
+      v[u] = (i <= j && j < n) ? G[i + (int64_t)j * ldg] : 0.0;
     }
-  if (ty == 0) {
 #pragma unroll
-    for (int b = 0; b < NBK; ++b) {
-      prow[0][tx + 64 * b] = Lr[0][b];
-      Rl[tx + 64 * b] = Lr[0][b];
+    for (int u = 0; u < PER; ++u) {
+      const int e = tid + u * CH_THREADS, i = e % CH_NMAX, j = e / CH_NMAX;
+      Rl[i * LDR + j] = v[u];
     }
   }
+  if (tid == 0) fail_sh = -1;
   __syncthreads();
-  const int tyu = __builtin_amdgcn_readfirstlane(ty);
-  int f = -1;
-  for (int j = 0; j < n; ++j) {
-    const int buf = j & 1;
-    const double piv = prow[buf][j];
-    double ri[NA], pk[NBK];
+  // The condition estimate of Rc runs on the last two waves (sigma_max,
+  // sigma_min), row by row as the rows become final: the rows of block
+  // K - 1 during phases A and B of block step K, the last block's at the
+  // end. Those waves take no part in phase C.
+  constexpr int NW = CH_THREADS / 64;
+  const bool ice_wave = w >= NW - 2;
+  IceWave<2> ice;
+  int ice_row = 0;  // next row of R for the estimate
+  auto ice_rows = [&](int upto) {
+    for (; ice_row < upto; ++ice_row) {
+      if (ice_row == 0) ice.start(Rl, n, 1, w == NW - 2);
+      else ice.step(Rl, n, LDR, 1, ice_row);
+    }
+  };
+  const int nb = (n + 15) / 16;
+  for (int K = 0; K < nb; ++K) {
+    const int k0 = 16 * K, kb = min(16, n - k0);
+    if (ice_wave && K > 0) ice_rows(k0 - 5);
+    if (w == 0) {
+      const int c = c16;
+      double col[16];
 #pragma unroll
-    for (int a = 0; a < NA; ++a) ri[a] = prow[buf][tyu + TY * a];
+      for (int i = 0; i < 16; ++i) col[i] = Rl[(k0 + i) * LDR + k0 + c];
+      int f = -1;
 #pragma unroll
-    for (int b = 0; b < NBK; ++b) pk[b] = prow[buf][tx + 64 * b];
-    if (!(piv > 0.0) || !isfinite(piv)) { f = j; break; }
-    const double inv = rcp_nr(piv);
-    double rk[NBK];
+      for (int j = 0; j < 16; ++j) {
+        // (wave-uniform conditions; no early exit, so the loops unroll)
+        const double piv = readlane_t(col[j], j);
+        if (j < kb && f < 0 && (!(piv > 0.0) || !isfinite(piv))) f = k0 + j;
+        if (j < kb && f < 0) {
+          const double inv = rsqrt_nr(piv), r = piv * inv;
+          col[j] = (c == j) ? r : col[j] * inv;
+          if (l == 0) dinv[j] = inv;
 #pragma unroll
-    for (int b = 0; b < NBK; ++b) rk[b] = pk[b] * inv;
-#pragma unroll
-    for (int a = 0; a < NA; ++a)
-#pragma unroll
-      for (int b = 0; b < NBK; ++b) Lr[a][b] = fma(-ri[a], rk[b], Lr[a][b]);
-    const int jn = j + 1;
-    if (jn < n && tyu == jn % TY) {
-      const int an = jn / TY;
-#pragma unroll
-      for (int a = 0; a < NA; ++a)
-        if (a == an) {
-#pragma unroll
-          for (int b = 0; b < NBK; ++b) {
-            prow[buf ^ 1][tx + 64 * b] = Lr[a][b];
-            Rl[jn * LDR + tx + 64 * b] = Lr[a][b];
+          for (int i = j + 1; i < 16; ++i) {
+            const double rji = readlane_t(col[j], i);
+            col[i] = fma(-rji, col[j], col[i]);
           }
         }
+      }
+      if (l < kb) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+          if (i <= c) Rl[(k0 + i) * LDR + k0 + c] = col[i];
+      }
+      if (l == 0 && f >= 0) fail_sh = f;
+    }
+    __syncthreads();
+    if (fail_sh >= 0) break;
+    const int cb = k0 + kb;  // first column right of the block
+    if (cb >= n) break;
+    if (ice_wave && K > 0) ice_rows(k0);
+    for (int c = cb + tid; c < n; c += CH_THREADS) {
+      double x[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) x[i] = Rl[(k0 + i) * LDR + c];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        x[i] *= dinv[i];
+#pragma unroll
+        for (int k = i + 1; k < 16; ++k) x[k] = fma(-Rl[(k0 + i) * LDR + k0 + k], x[i], x[k]);
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) Rl[(k0 + i) * LDR + c] = x[i];
+    }
+    __syncthreads();
+    // trailing tiles (I, J), K < I <= J < nb, numbered row by row
+    const int nt = nb - K - 1;
+    for (int t = w; t < nt * (nt + 1) / 2 && !ice_wave; t += NW - 2) {
+      int a = 0, rem = t;
+      while (rem >= nt - a) { rem -= nt - a; ++a; }
+      const int I = K + 1 + a, J = I + rem;
+      f64x4 acc = f64x4{0, 0, 0, 0};
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const double* rk = Rl + (k0 + 4 * s + g) * LDR;
+        acc = mfma_f64(rk[16 * I + c16], rk[16 * J + c16], acc);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Rl[(16 * I + 4 * r + g) * LDR + 16 * J + c16] -= acc[r];
     }
     __syncthreads();
   }
-  // rows i < nrows = (f < 0 ? n : f) of Rl hold the Schur rows; zero the
-  // strict lower triangle and the rows past a breakdown, scale row i by
-  // 1/sqrt(piv_i) (diagonal: sqrt(piv_i))
-  const int nrows = (f < 0) ? n : f;
-  __syncthreads();
-  if (tid < n) {
-    const double d = Rl[tid * LDR + tid];
-    rscale[tid] = (tid < nrows) ? 1.0 / sqrt(d) : 0.0;
+  // Rc leaves from the other waves while the estimate takes the last rows
+  const int f = fail_sh;
+  __shared__ double ice_res[2];
+  if (ice_wave) {
+    if (f < 0) {
+      ice_rows(n);
+      if (l == 0) ice_res[w - (NW - 2)] = ice.estimate();
+    }
+  } else {
+    for (int e = tid; e < n * n; e += CH_THREADS - 128) {
+      const int i = e % n, k = e / n;
+      Rc[i + (int64_t)k * ldr] = (f < 0 && i <= k) ? Rl[i * LDR + k] : 0.0;
+    }
   }
   __syncthreads();
-  for (int e = tid; e < n * n; e += CH_THREADS) {
-    const int i = e / n, k = e % n;
-    double v = 0.0;
-    if (i < nrows && k >= i) v = (k == i) ? sqrt(Rl[i * LDR + i]) : Rl[i * LDR + k] * rscale[i];
-    Rl[i * LDR + k] = v;
-  }
-  __syncthreads();
-  for (int k = tx; k < n; k += 64)
-    for (int i = ty; i < n; i += TY) Rc[i + (int64_t)k * ldr] = (f < 0) ? Rl[i * LDR + k] : 0.0;
   {
-    double kappa = ice_kappa_block(Rl, n, LDR, 1, f < 0);
-    if (f >= 0) kappa = __builtin_inf();
+    double kappa = __builtin_inf();
+    if (f < 0) {
+      const double eM = ice_res[0], em = ice_res[1];
+      kappa = (!isfinite(eM) || !isfinite(em) || !(em > 0.0)) ? __builtin_inf() : eM / em;
+    }
     if (tid == 0) {
       if (fail_out) *fail_out = f;
       if (kappa_out) *kappa_out = kappa;

@@ -44,52 +44,85 @@ __device__ __forceinline__ double sqrt_nr(double x) {
   return x > 0.0 ? q : 0.0;
 }
 
-// One ICE update (s, c, est_new) from est, alpha = w^T x and gamma, written
-// without branches so that the sigma_max and sigma_min updates of a step
+// Reciprocal and reciprocal square root with one Newton step from the
+// hardware estimates, for the condition estimate only (a loose quantity:
+// the step doubles the estimate's correct bits, which is ample here).
+__device__ __forceinline__ double rcp1(double d) {
+  const double y = __builtin_amdgcn_rcp(d);
+  return fma(y, fma(-d, y, 1.0), y);
+}
+__device__ __forceinline__ double rsqrt1(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  return fma(y, fma(-0.5 * x * y, y, 0.5), y);
+}
+
+// One ICE update. The estimate is kept as est = sqrt(es2) 2^F (es2 < 4),
+// so that no square root sits on its chain and no square overflows: with
+// 2^E >= rho = max(est, |alpha|, |gamma|) (E from exponents only; exact
+// power-of-two scaling) M = [[e^2 + a^2, a g], [a g, g^2]] for the scaled
+// values, lam_max from the closed form, lam_min = (e g)^2 / lam_max, (s, c)
+// the unit eigenvector of the chosen eigenvalue, and the new estimate is
+// sqrt(lam) 2^E. Branch-free so that the sigma_max and sigma_min updates
 // run interleaved.
-__device__ __forceinline__ void ice_step(double est, double alpha, double gamma, bool largest,
-                                         double& s, double& c, double& est_new) {
-  const double rho = fmax(fmax(est, fabs(alpha)), fabs(gamma));
-  // rho is scaled by a power of two so the scaling is exact
-  int erho;
-  (void)frexp(rho, &erho);
-  const double e = ldexp(est, -erho), a = ldexp(alpha, -erho), g = ldexp(gamma, -erho);
-  const double A = fma(e, e, a * a), B = a * g, C = g * g;
+__device__ __forceinline__ void ice_step(double& es2, int& F, double alpha, double gamma, bool largest,
+                                         double& s, double& c) {
+  int ke, ka, kg;
+  (void)frexp(es2, &ke);
+  (void)frexp(alpha, &ka);
+  (void)frexp(gamma, &kg);
+  const int E = max(max(F + ((ke + 1) >> 1), ka), kg);
+  const double e2s = ldexp(es2, 2 * (F - E)), a = ldexp(alpha, -E), g = ldexp(gamma, -E);
+  const double A = fma(a, a, e2s), B = a * g, C = g * g;
   const double hd = 0.5 * (A - C);
-  const double lmax = 0.5 * (A + C) + sqrt_nr(fma(hd, hd, B * B));
-  const double eg = e * g;
-  const double lam = largest ? lmax : (eg * eg) * rcp_nr(lmax > 0.0 ? lmax : 1.0);
+  const double disc = fma(hd, hd, B * B);
+  const double lmax = 0.5 * (A + C) + (disc > 0.0 ? disc * rsqrt1(disc) : 0.0);
+  const double lam = largest ? lmax : (e2s * C) * rcp1(lmax > 0.0 ? lmax : 1.0);
   const double v1a = lam - C, v2b = lam - A;
   const double n1 = fma(v1a, v1a, B * B), n2 = fma(v2b, v2b, B * B);
   const bool first = n1 >= n2;
   const double va = first ? v1a : B, vb = first ? B : v2b, nn = first ? n1 : n2;
   const bool deg = !(nn > 0.0);
-  const double r = rsqrt_nr(deg ? 1.0 : nn);
+  const double r = rsqrt1(deg ? 1.0 : nn);
   s = deg ? (largest ? 0.0 : 1.0) : va * r;
   c = deg ? (largest ? 1.0 : 0.0) : vb * r;
-  est_new = ldexp(sqrt_nr(fmax(lam, 0.0)), erho);
-  if (rho == 0.0) { s = 1.0; c = 0.0; est_new = 0.0; }
+  const bool zero = es2 == 0.0 && alpha == 0.0 && gamma == 0.0;
+  if (zero) { s = 1.0; c = 0.0; }
+  es2 = zero ? 0.0 : fmax(lam, 0.0);
+  F = zero ? F : E;
 }
 
-// ICE estimate of sigma_max (LARGEST) or sigma_min of R (element (i, j) at
-// R[i*si + j*sj]) by one full wave; n <= 64 * XPL. Returns NaN when R holds
-// a non-finite value. Right-looking form of alpha_j = R[0:j, j]^T x: lane l
-// keeps beta_k = R[0:j, k]^T x for its columns k = l + 64 q, and the step
-// that turns x into [s x; c] updates beta_k <- s beta_k + c R[j, k].
-// alpha_j is then read from the lane holding column j, so no reduction sits
-// on the serial chain; rows of R are read contiguously when si = ld, sj = 1.
-template <int XPL, bool LARGEST>
-__device__ double ice_est_wave(const double* R, int n, int si, int sj) {
-  const int l = threadIdx.x & 63;
+// ICE of sigma_max (largest) or sigma_min of R (element (i, j) at
+// R[i*si + j*sj], n <= 64 * XPL) by one full wave, row by row: start()
+// takes row 0, step(j) row j (rows in order), estimate() the result (NaN
+// when R holds a non-finite value). Right-looking form of
+// alpha_j = R[0:j, j]^T x: lane l keeps beta_k = R[0:j, k]^T x for its
+// columns k = l + 64 q, and the step that turns x into [s x; c] updates
+// beta_k <- s beta_k + c R[j, k]. alpha_j is read from the lane holding
+// column j, so no reduction sits on the serial chain; rows of R are read
+// contiguously when si = ld, sj = 1. A caller may interleave the steps with
+// other work, once the rows they read are final.
+template <int XPL>
+struct IceWave {
   double b[XPL];
+  double es2;
+  int F;
+  bool bad, largest;
+
+  __device__ void start(const double* R, int n, int sj, bool lg) {
+    largest = lg;
+    const int l = threadIdx.x & 63;
 #pragma unroll
-  for (int q = 0; q < XPL; ++q) {
-    const int k = l + 64 * q;
-    b[q] = (k < n) ? R[k * sj] : 0.0;  // x = [1]: beta_k = R[0, k]
+    for (int q = 0; q < XPL; ++q) {
+      const int k = l + 64 * q;
+      b[q] = (k < n) ? R[k * sj] : 0.0;  // x = [1]: beta_k = R[0, k]
+    }
+    const double r00 = R[0];
+    const double m00 = frexp(r00, &F);  // |r00| = |m00| 2^F
+    es2 = m00 * m00;
+    bad = !isfinite(r00);
   }
-  double est = fabs(R[0]);
-  bool bad = !isfinite(est);
-  for (int j = 1; j < n; ++j) {
+  __device__ void step(const double* R, int n, int si, int sj, int j) {
+    const int l = threadIdx.x & 63;
     double row[XPL];
 #pragma unroll
     for (int q = 0; q < XPL; ++q) {
@@ -105,11 +138,19 @@ __device__ double ice_est_wave(const double* R, int n, int si, int sj) {
     const double alpha = readlane_t(v, j & 63);
     bad |= !isfinite(gma) || !isfinite(alpha);
     double sn, cs;
-    ice_step(est, alpha, gma, LARGEST, sn, cs, est);
+    ice_step(es2, F, alpha, gma, largest, sn, cs);
 #pragma unroll
     for (int q = 0; q < XPL; ++q) b[q] = fma(sn, b[q], cs * row[q]);
   }
-  return bad ? __builtin_nan("") : est;
+  __device__ double estimate() const { return bad ? __builtin_nan("") : ldexp(sqrt(es2), F); }
+};
+
+template <int XPL, bool LARGEST>
+__device__ double ice_est_wave(const double* R, int n, int si, int sj) {
+  IceWave<XPL> ice;
+  ice.start(R, n, sj, LARGEST);
+  for (int j = 1; j < n; ++j) ice.step(R, n, si, sj, j);
+  return ice.estimate();
 }
 
 // kappa estimate est_max / est_min of R: sigma_max on wave 0 and sigma_min
