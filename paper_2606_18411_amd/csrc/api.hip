@@ -8,7 +8,8 @@
 #include "mrcqr.h"
 
 namespace mrcqr {
-hipError_t launch_draw(uint64_t seed, int m, int s, int32_t* S, int8_t* D, hipStream_t st);
+hipError_t launch_draw(uint64_t seed, int m, int s, int32_t* S, int8_t* D, hipStream_t st, Ctrl* ctrl = nullptr,
+                       int prec = 0, int auto_mode = 0);
 hipError_t launch_sketch(int prec, const double* A, int64_t lda, int m, int n, const int32_t* S, int s,
                          uint64_t seed, void* Ypart, double* Y, int64_t ldy, const Ctrl* ctrl, int phase,
                          hipStream_t st);
@@ -29,9 +30,10 @@ hipError_t launch_trmm(const double* R2, int64_t ld2, const double* R1, int64_t 
                        int64_t ldr, const Ctrl* ctrl, int phase, hipStream_t st);
 hipError_t launch_trinv(const double* R, int n, int64_t ldr, double* X, int64_t ldx, const Ctrl* ctrl, int phase,
                         hipStream_t st);
+hipError_t launch_rc_tail(const double* Rc, int n, int64_t ldc, const double* Rs, int64_t ldrs, double* X, int64_t ldx,
+                          double* R, int64_t ldr, const Ctrl* ctrl, int phase, hipStream_t st);
 hipError_t launch_qform(const double* B, int m, int n, int64_t ldb, const double* X, int64_t ldx, double* Q,
                         int64_t ldq, const Ctrl* ctrl, int phase, hipStream_t st);
-hipError_t launch_ctrl_init(Ctrl* ctrl, int prec, int auto_mode, hipStream_t st);
 hipError_t launch_ctrl_finalize(const Ctrl* ctrl, void* info, hipStream_t st);
 }  // namespace mrcqr
 
@@ -104,8 +106,8 @@ static int execute(const mrcqr_plan* p, char* ws, const double* A, int64_t lda, 
   const int64_t ldb = p->m;
   hipError_t e;
   const bool automode = prec == MRCQR_PREC_AUTO;
-  if ((e = launch_ctrl_init(ctrl, automode ? P_FP16 : prec, automode ? 1 : 0, st)) != hipSuccess) return MRCQR_ERR_DEVICE;
-  if ((e = launch_draw(seed, m, s, S, nullptr, st)) != hipSuccess) return MRCQR_ERR_DEVICE;
+  if ((e = launch_draw(seed, m, s, S, nullptr, st, ctrl, automode ? P_FP16 : prec, automode ? 1 : 0)) != hipSuccess)
+    return MRCQR_ERR_DEVICE;
   // The launch sequence is static: in AUTO every attempt is enqueued and
   // the kernels of an attempt whose precision is not the current one (or of
   // a rerun that was not requested) return immediately.
@@ -117,9 +119,8 @@ static int execute(const mrcqr_plan* p, char* ws, const double* A, int64_t lda, 
     return launch_trsm(A, m, n, lda, Rs, n, B, ldb, Tw, ctrl, phase, st) == hipSuccess &&
            launch_gram(B, m, n, ldb, Gpart, G, n, ctrl, phase, st) == hipSuccess &&
            launch_cholesky(G, n, n, Rc, n, nullptr, nullptr, ctrl, phase, st) == hipSuccess &&
-           launch_trinv(Rc, n, n, Rci, n, ctrl, tail_phase, st) == hipSuccess &&
-           launch_qform(B, m, n, ldb, Rci, n, Q, ldq, ctrl, tail_phase, st) == hipSuccess &&
-           launch_trmm(Rc, n, Rs, n, n, R, ldr, ctrl, tail_phase, st) == hipSuccess;
+           launch_rc_tail(Rc, n, n, Rs, n, Rci, n, R, ldr, ctrl, tail_phase, st) == hipSuccess &&
+           launch_qform(B, m, n, ldb, Rci, n, Q, ldq, ctrl, tail_phase, st) == hipSuccess;
   };
   if (automode) {
     for (int pp : {P_FP16, P_FP32, P_FP64})

@@ -7,12 +7,12 @@
 // per-call control kernels.
 #include "common.hpp"
 #include "ice.hpp"
+#include "small.hpp"
 
 namespace mrcqr {
 
 constexpr int CH_THREADS = 512;
 constexpr int CH_NMAX = 128;
-constexpr int TRMM_NMAX = 128;
 
 // Blocked right-looking Cholesky of the upper triangle of G (n <= 128),
 // 16-column blocks, all of it in LDS (row-major, stride 129). Block step K:
@@ -182,99 +182,14 @@ __global__ __launch_bounds__(CH_THREADS) void chol_kernel(
   }
 }
 
-// R = R2 R1 (upper x upper), each entry sum_{j=i..k} R2[i][j] R1[j][k]
-// accumulated in index order.
+// Stage 3, stand-alone: R = R2 R1 (see trmm_tile).
 __global__ __launch_bounds__(64) void trmm_kernel(const double* __restrict__ R2, int64_t ld2,
                                                   const double* __restrict__ R1, int64_t ld1, int n,
                                                   double* __restrict__ R, int64_t ldr,
                                                   const Ctrl* __restrict__ ctrl, int phase) {
-  // one wave per (64-row block, 16-column block): lane l accumulates row
-  // i = 64 blockIdx.y + l of the 16 columns c0..c0+15. The needed parts of
-  // R2 (rows i0..i0+63, columns i0..jend-1) and of R1 (rows 0..jend-1,
-  // the 16 columns) are staged in LDS first. Only the upper triangles of
-  // R1 and R2 are read as values.
-  __shared__ __attribute__((aligned(16))) double r1s[TRMM_NMAX * 16];
-  __shared__ __attribute__((aligned(16))) double r2s[64 * TRMM_NMAX];
+  __shared__ __attribute__((aligned(16))) double lds[TRMM_LDS_DOUBLES];
   if (skip_launch(ctrl, P_AUTO, phase)) return;
-  const int l = threadIdx.x;
-  const int c0 = 16 * blockIdx.x, i0 = 64 * blockIdx.y;
-  const int i = i0 + l;
-  const int jend = min(n, c0 + 16);  // R1[j][c] = 0 for j > c
-  // loads with clamped (always valid) addresses and no branches, so that
-  // they are all in flight together; the masks are applied afterwards
-  {
-    double v[32];
-#pragma unroll
-    for (int u = 0; u < 32; ++u) {
-      const int e = l + 64 * u, j = min(e / 16, n - 1), c = e % 16;
-      v[u] = R1[j + (int64_t)min(c0 + c, n - 1) * ld1];
-    }
-#pragma unroll
-    for (int u = 0; u < 32; ++u) {
-      const int e = l + 64 * u, j = e / 16, c = e % 16;
-      if (e < jend * 16) r1s[e] = (c0 + c < n && j <= c0 + c) ? v[u] : 0.0;
-    }
-  }
-  // R2[i][j] for j in [i0, jend), column-major in LDS (64 rows per column).
-  // A full 64-row block with an even leading dimension is copied by direct
-  // global-to-LDS loads (two columns of 16-byte pairs per instruction, all
-  // in flight together); otherwise element by element.
-  const bool direct = (i0 + 64 <= n) && ((ld2 & 1) == 0) && ((reinterpret_cast<uintptr_t>(R2) & 15) == 0);
-  if (direct) {
-    typedef __attribute__((address_space(3))) void lds_t;
-    const int ncol = jend - i0;
-    for (int k = 0; 2 * k < ncol; ++k) {
-      const int jj = min(2 * k + (l >> 5), ncol - 1);
-      const double* src = R2 + (i0 + 2 * (l & 31)) + (int64_t)(i0 + jj) * ld2;
-      __builtin_amdgcn_global_load_lds(src, (lds_t*)(r2s + 128 * k), 16, 0, 0);
-    }
-    __builtin_amdgcn_s_waitcnt(0);
-  } else {
-    const int ic = min(i, n - 1);
-    for (int j0 = i0; j0 < jend; j0 += 16) {
-      double v[16];
-#pragma unroll
-      for (int u = 0; u < 16; ++u) v[u] = R2[ic + (int64_t)min(j0 + u, n - 1) * ld2];
-#pragma unroll
-      for (int u = 0; u < 16; ++u)
-        if (j0 + u < jend) r2s[(j0 + u - i0) * 64 + l] = v[u];
-    }
-  }
-  __syncthreads();
-  // only the upper triangle of R2 is a value: zero row i's entries j < i
-  // (all of them for rows past n), then the product loop has no branches
-  const int ncol = jend - i0;
-  const int zlim = (i < n) ? min(l, ncol) : ncol;
-  for (int jj = 0; jj < zlim; ++jj) r2s[jj * 64 + l] = 0.0;
-  __syncthreads();
-  double acc[16];
-#pragma unroll
-  for (int c = 0; c < 16; ++c) acc[c] = 0.0;
-#pragma unroll 4
-  for (int jj = 0; jj < ncol; ++jj) {
-    const double a = r2s[jj * 64 + l];
-    const double* rr = r1s + (i0 + jj) * 16;
-#pragma unroll
-    for (int c = 0; c < 16; ++c) acc[c] = fma(a, rr[c], acc[c]);
-  }
-  if (i < n) {
-#pragma unroll
-    for (int c = 0; c < 16; ++c)
-      if (c0 + c < n) R[i + (int64_t)(c0 + c) * ldr] = acc[c];
-  }
-}
-
-__global__ void ctrl_init_kernel(Ctrl* ctrl, int prec, int auto_mode) {
-  if (threadIdx.x == 0) {
-    ctrl->cur_prec = prec;
-    ctrl->status = ST_OK;
-    ctrl->chol_fail = -1;
-    ctrl->escalations = 0;
-    ctrl->auto_mode = auto_mode;
-    ctrl->retry = 0;
-    ctrl->kappa_rs = 0.0;
-    ctrl->kappa_rc = 0.0;
-  }
+  trmm_tile(R2, ld2, R1, ld1, n, R, ldr, blockIdx.x, blockIdx.y, lds);
 }
 
 struct InfoOut {
@@ -307,11 +222,6 @@ hipError_t launch_trmm(const double* R2, int64_t ld2, const double* R1, int64_t 
   if (n > TRMM_NMAX) return hipErrorInvalidValue;
   hipLaunchKernelGGL(trmm_kernel, dim3((n + 15) / 16, (n + 63) / 64), dim3(64), 0, st, R2, ld2, R1, ld1, n, R, ldr,
                      ctrl, phase);
-  return hipGetLastError();
-}
-
-hipError_t launch_ctrl_init(Ctrl* ctrl, int prec, int auto_mode, hipStream_t st) {
-  hipLaunchKernelGGL(ctrl_init_kernel, dim3(1), dim3(64), 0, st, ctrl, prec, auto_mode);
   return hipGetLastError();
 }
 

@@ -88,6 +88,18 @@ constexpr double TAU_FP32 = 1e8;
 constexpr double TAU_BF16 = 1e2;
 constexpr double TAU_POSTERIOR = 20.0;
 
+// Start-of-call state of the control block (one thread writes it).
+__device__ __forceinline__ void ctrl_reset(Ctrl* ctrl, int prec, int auto_mode) {
+  ctrl->cur_prec = prec;
+  ctrl->status = ST_OK;
+  ctrl->chol_fail = -1;
+  ctrl->escalations = 0;
+  ctrl->auto_mode = auto_mode;
+  ctrl->retry = 0;
+  ctrl->kappa_rs = 0.0;
+  ctrl->kappa_rc = 0.0;
+}
+
 // Launch gating of the static launch sequence (no host round trip):
 //   phase 0: first pass, always runs;
 //   phase 1: rerun pass, runs only when the posterior check asked for it;

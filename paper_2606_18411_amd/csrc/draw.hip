@@ -60,7 +60,11 @@ __device__ void bitonic_sort(uint32_t* keys, int P) {
   }
 }
 
-__global__ __launch_bounds__(DRAW_THREADS) void draw_kernel(uint64_t seed, int m, int s, int32_t* S_out) {
+// With a control block, thread 0 also resets it for a new factorization
+// (the first launch of the call).
+__global__ __launch_bounds__(DRAW_THREADS) void draw_kernel(uint64_t seed, int m, int s, int32_t* S_out,
+                                                            Ctrl* ctrl, int prec, int auto_mode) {
+  if (ctrl && threadIdx.x == 0) ctrl_reset(ctrl, prec, auto_mode);
   __shared__ uint32_t keys[DRAW_SMAX];
   __shared__ int dup;
   const uint64_t key1 = stream_key(seed, 1);
@@ -114,11 +118,12 @@ __global__ void signs_kernel(uint64_t seed, int m, int8_t* D) {
     D[t] = (hash_at(key0, (uint64_t)t) >> 63) ? (int8_t)-1 : (int8_t)1;
 }
 
-hipError_t launch_draw(uint64_t seed, int m, int s, int32_t* S, int8_t* D, hipStream_t st) {
+hipError_t launch_draw(uint64_t seed, int m, int s, int32_t* S, int8_t* D, hipStream_t st, Ctrl* ctrl, int prec,
+                       int auto_mode) {
   int P = 1;
   while (P < s) P <<= 1;
   const int threads = P <= DRAW_THREADS ? (P < 64 ? 64 : P) : DRAW_THREADS;
-  hipLaunchKernelGGL(draw_kernel, dim3(1), dim3(threads), 0, st, seed, m, s, S);
+  hipLaunchKernelGGL(draw_kernel, dim3(1), dim3(threads), 0, st, seed, m, s, S, ctrl, prec, auto_mode);
   if (D) {
     int blocks = (m + 255) / 256;
     if (blocks > 4096) blocks = 4096;

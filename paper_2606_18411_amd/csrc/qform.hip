@@ -10,12 +10,9 @@
 // into a streaming float64 MFMA contraction. Rs is never inverted:
 // B = A Rs^{-1} stays a substitution.
 //
-// trinv_kernel: X = R^{-1} for upper-triangular R, one wave per column j
-// of X. The wave solves R x = e_j by back substitution
-// (x_i = (e_j - sum_{k>i} r_ik x_k)_i / r_ii for i = j..0) in column order:
-// once x_i is known, r_ki x_i is taken off the right-hand side of every
-// row k < i. Lane l holds rows l and l + 64; x_i is formed on the lane
-// holding row i (with that lane's reciprocal of r_ii) and read from there.
+// trinv_kernel / rc_tail_kernel: X = R^{-1} for upper-triangular R, one
+// wave per column (trinv_column); in the factorization the same launch also
+// forms R = Rc Rs.
 //
 // qform_kernel<NB>: Q = B X with X upper triangular (NB = ceil(n / 16)
 // blocks of 16 columns). X is staged once per workgroup in LDS in MFMA
@@ -29,6 +26,7 @@
 // whatever q is, in chunks of 8 steps; up to three chunks ahead (of this
 // tile or the next) are loaded while one is multiplied.
 #include "common.hpp"
+#include "small.hpp"
 
 namespace mrcqr {
 
@@ -38,46 +36,31 @@ constexpr int QF_CH = 4;  // K-step pairs per chunk
 
 __host__ __device__ constexpr int qf_off(int J, int q) { return 64 * (2 * J * (J + 1) + q); }
 
-// Column solves of trinv_kernel: wave v of block b solves column j = 2 b + v.
-__global__ __launch_bounds__(128) void trinv_kernel(const double* __restrict__ R, int n, int64_t ldr,
-                                                    double* __restrict__ X, int64_t ldx,
-                                                    const Ctrl* __restrict__ ctrl, int phase) {
+// Stand-alone X = R^{-1}: one 64-thread workgroup per column (see
+// trinv_column).
+__global__ __launch_bounds__(64) void trinv_kernel(const double* __restrict__ R, int n, int64_t ldr,
+                                                   double* __restrict__ X, int64_t ldx,
+                                                   const Ctrl* __restrict__ ctrl, int phase) {
   if (skip_launch(ctrl, P_AUTO, phase)) return;
-  constexpr int U = 8;
-  const int j = 2 * blockIdx.x + (threadIdx.x >> 6), l = threadIdx.x & 63;
-  if (j >= n) return;
-  const int ra = min(l, n - 1), rb = min(l + 64, n - 1);  // clamped: always valid addresses
-  // each lane's own rows' reciprocal diagonal: x_i is formed on the lane
-  // that holds row i and read from there
-  const double rinv0 = 1.0 / R[ra + (int64_t)ra * ldr], rinv1 = 1.0 / R[rb + (int64_t)rb * ldr];
-  double s0 = (l == j) ? 1.0 : 0.0, s1 = (l + 64 == j) ? 1.0 : 0.0;
-  double pa[U], pb[U];
-  auto fetch = [&](int i0) {
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t i = max(i0 - u, 0);
-      pa[u] = R[ra + i * ldr];
-      pb[u] = R[rb + i * ldr];
-    }
-  };
-  fetch(j);
-  for (int i0 = j; i0 >= 0; i0 -= U) {
-    double ca[U], cb[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) { ca[u] = pa[u]; cb[u] = pb[u]; }
-    if (i0 - U >= 0) fetch(i0 - U);
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int i = i0 - u;
-      if (i < 0) break;
-      const double own = (i < 64) ? s0 * rinv0 : s1 * rinv1;
-      const double x = readlane_t(own, i & 63);
-      s0 = (l == i) ? x : ((l < i) ? fma(-ca[u], x, s0) : s0);
-      s1 = (l + 64 == i) ? x : ((l + 64 < i) ? fma(-cb[u], x, s1) : s1);
-    }
+  trinv_column(R, n, ldr, X, ldx, blockIdx.x);
+}
+
+// The small steps after the Cholesky of the factorization in one launch:
+// workgroups 0..n-1 form the columns of Rc^{-1} for Q, the rest the tiles of
+// Stage 3's R = Rc Rs (independent of each other).
+__global__ __launch_bounds__(64) void rc_tail_kernel(const double* __restrict__ Rc, int n, int64_t ldc,
+                                                     const double* __restrict__ Rs, int64_t lds_,
+                                                     double* __restrict__ X, int64_t ldx, double* __restrict__ R,
+                                                     int64_t ldr, const Ctrl* __restrict__ ctrl, int phase) {
+  __shared__ __attribute__((aligned(16))) double lds[TRMM_LDS_DOUBLES];
+  if (skip_launch(ctrl, P_AUTO, phase)) return;
+  const int b = blockIdx.x;
+  if (b < n) {
+    trinv_column(Rc, n, ldc, X, ldx, b);
+    return;
   }
-  if (l < n) X[l + (int64_t)j * ldx] = s0;
-  if (l + 64 < n) X[l + 64 + (int64_t)j * ldx] = s1;
+  const int t = b - n, nbx = (n + 15) / 16;
+  trmm_tile(Rc, ldc, Rs, lds_, n, R, ldr, t % nbx, t / nbx, lds);
 }
 
 template <int NB, int NT>
@@ -291,7 +274,16 @@ __global__ __launch_bounds__(NT == 2 ? 256 : 512) void qform_kernel(
 hipError_t launch_trinv(const double* R, int n, int64_t ldr, double* X, int64_t ldx, const Ctrl* ctrl, int phase,
                         hipStream_t st) {
   if (n > QF_NMAX) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(trinv_kernel, dim3((n + 1) / 2), dim3(128), 0, st, R, n, ldr, X, ldx, ctrl, phase);
+  hipLaunchKernelGGL(trinv_kernel, dim3(n), dim3(64), 0, st, R, n, ldr, X, ldx, ctrl, phase);
+  return hipGetLastError();
+}
+
+hipError_t launch_rc_tail(const double* Rc, int n, int64_t ldc, const double* Rs, int64_t ldrs, double* X, int64_t ldx,
+                          double* R, int64_t ldr, const Ctrl* ctrl, int phase, hipStream_t st) {
+  if (n > QF_NMAX || n > TRMM_NMAX) return hipErrorInvalidValue;
+  const int tiles = ((n + 15) / 16) * ((n + 63) / 64);
+  hipLaunchKernelGGL(rc_tail_kernel, dim3(n + tiles), dim3(64), 0, st, Rc, n, ldc, Rs, ldrs, X, ldx, R, ldr, ctrl,
+                     phase);
   return hipGetLastError();
 }
 
