@@ -11,9 +11,10 @@ namespace mrcqr {
 
 constexpr int GR_THREADS = 512;
 constexpr int GR_PANEL = 64;
+constexpr int GR_SLAB = 256;  // rows per slab (the solve's rows per workgroup pass)
 constexpr int GR_NMAX = 128;
 constexpr int GR_NB = GR_NMAX / 16;
-constexpr int GR_LDR = 66;  // column stride (doubles) of the LDS panel
+constexpr int GR_LDR = 65;  // column stride (doubles) of the LDS panel (odd: conflict-free operand reads)
 constexpr int GR_TPW = 5;   // upper tiles per wave (at most)
 
 // Upper tile u of wave w (8 waves, 8 x 8 tile grid, 36 tiles): waves 0-3
@@ -29,22 +30,34 @@ __device__ __forceinline__ void gr_tile(int w, int u, int& I, int& J) {
   else { I = GR_NB; J = GR_NB; }  // no tile
 }
 
-// The panel is column-major in LDS with a 66-double column stride:
+// The panel is column-major in LDS with a 65-double column stride:
 // coalesced 64-row column stores and the operand reads (16 columns x 4 rows
 // per wave) both hit distinct banks. Per K step (4 rows) a wave reads the A
 // operand of each of its block rows once and one B operand per tile, and
 // issues one float64 MFMA 16x16x4 per tile.
+// Rows are taken in slabs of GR_SLAB: chunk c owns slabs c, c + chunks,
+// c + 2 chunks, ... (the slabs the triangular solve's workgroup c writes, in
+// the same 256-row units) and reads them last-written first, so that its
+// first panels are still in the memory-side cache.
 __global__ __launch_bounds__(GR_THREADS) void syrk_kernel(
-    const double* __restrict__ B, int m, int n, int64_t ldb, int rows_per_chunk,
+    const double* __restrict__ B, int m, int n, int64_t ldb, int chunks,
     double* __restrict__ Gpart, const Ctrl* __restrict__ ctrl, int phase) {
   __shared__ double tile[2][GR_NMAX * GR_LDR];
   if (skip_launch(ctrl, P_AUTO, phase)) return;
   const int tid = threadIdx.x;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63, g = l >> 4, c16 = l & 15;
   const int nb = (n + 15) / 16;
-  const int64_t tstart = (int64_t)blockIdx.x * rows_per_chunk;
-  const int64_t tend = min((int64_t)m, tstart + rows_per_chunk);
-  const int npan = (int)((tend - tstart + GR_PANEL - 1) / GR_PANEL);
+  const int64_t nslab = ((int64_t)m + GR_SLAB - 1) / GR_SLAB;
+  const int c = blockIdx.x;
+  const int nsc = (int)((nslab - c + chunks - 1) / chunks);  // slabs of this chunk
+  constexpr int PPS = GR_SLAB / GR_PANEL;                    // panels per slab
+  const int npan = nsc * PPS;
+  // first row of this chunk's panel i (slabs in reverse order)
+  auto panel_row = [&](int i) -> int64_t {
+    const int64_t slab = c + (int64_t)chunks * (nsc - 1 - i / PPS);
+    return slab * GR_SLAB + (int64_t)GR_PANEL * (i % PPS);
+  };
+  const int64_t tend = m;
 
   int ti[GR_TPW], tj[GR_TPW];
   bool has[GR_TPW];
@@ -75,12 +88,12 @@ __global__ __launch_bounds__(GR_THREADS) void syrk_kernel(
       }
     }
   };
-  if (npan > 0) load_panel(tstart);
+  if (npan > 0) load_panel(panel_row(0));
   for (int p = 0; p < npan; ++p) {
     const int buf = p & 1;
 #pragma unroll
     for (int e = 0; e < EPT; ++e) tile[buf][(w + CST * e) * GR_LDR + l] = regs[e];
-    if (p + 1 < npan) load_panel(tstart + (int64_t)(p + 1) * GR_PANEL);
+    if (p + 1 < npan) load_panel(panel_row(p + 1));
     __syncthreads();
     const double* tb = tile[buf] + c16 * GR_LDR + g;
     // no branches in the K loop: a tile that does not exist (beyond nb)
@@ -164,29 +177,22 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const double* __restri
   }
 }
 
-struct GramGeom { int chunks, rows_per_chunk; };
-
-GramGeom gram_geometry(int64_t m) {
-  const int64_t npan = (m + GR_PANEL - 1) / GR_PANEL;
-  const int64_t target = 256;  // one workgroup per compute unit
-  const int64_t per = (npan + target - 1) / target;
-  GramGeom gg;
-  gg.rows_per_chunk = (int)(per * GR_PANEL);
-  gg.chunks = (int)((m + gg.rows_per_chunk - 1) / gg.rows_per_chunk);
-  return gg;
+// one workgroup per compute unit, at most one per slab
+static int gram_chunks(int64_t m) {
+  const int64_t nslab = (m + GR_SLAB - 1) / GR_SLAB;
+  return (int)(nslab < 256 ? nslab : 256);
 }
 
 size_t gram_partial_bytes(int64_t m, int64_t n) {
-  GramGeom gg = gram_geometry(m);
-  return (size_t)gg.chunks * (size_t)n * (size_t)n * sizeof(double);
+  return (size_t)gram_chunks(m) * (size_t)n * (size_t)n * sizeof(double);
 }
 
 hipError_t launch_gram(const double* B, int m, int n, int64_t ldb, double* Gpart, double* G, int64_t ldg,
                        const Ctrl* ctrl, int phase, hipStream_t st) {
   if (n > GR_NMAX) return hipErrorInvalidValue;
-  GramGeom gg = gram_geometry(m);
-  hipLaunchKernelGGL(syrk_kernel, dim3(gg.chunks), dim3(GR_THREADS), 0, st, B, m, n, ldb, gg.rows_per_chunk, Gpart, ctrl, phase);
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3(n), dim3(256), 0, st, (const double*)Gpart, gg.chunks, n, G, ldg, ctrl, phase);
+  const int chunks = gram_chunks(m);
+  hipLaunchKernelGGL(syrk_kernel, dim3(chunks), dim3(GR_THREADS), 0, st, B, m, n, ldb, chunks, Gpart, ctrl, phase);
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3(n), dim3(256), 0, st, (const double*)Gpart, chunks, n, G, ldg, ctrl, phase);
   return hipGetLastError();
 }
 
