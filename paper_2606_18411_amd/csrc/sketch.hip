@@ -32,7 +32,7 @@ template <int P> struct SkT;
 template <> struct SkT<P_FP16> { using elem = _Float16; using acc = float; static constexpr int KSTEP = 32; static constexpr int LD = 72; };
 template <> struct SkT<P_BF16> { using elem = __bf16;   using acc = float; static constexpr int KSTEP = 32; static constexpr int LD = 72; };
 template <> struct SkT<P_FP32> { using elem = float;    using acc = float; static constexpr int KSTEP = 4;  static constexpr int LD = 66; };
-template <> struct SkT<P_FP64> { using elem = double;   using acc = double; static constexpr int KSTEP = 4; static constexpr int LD = 66; };
+template <> struct SkT<P_FP64> { using elem = double;   using acc = double; static constexpr int KSTEP = 4; static constexpr int LD = 65; };
 
 // ---- cos/sin of the DCT-II phase --------------------------------------
 // angle = (pi/2) * phi / m for an integer phase phi in [0, 4m).
@@ -233,6 +233,8 @@ __global__ __launch_bounds__(SK_THREADS) void sketch_kernel(
         if ((l & 7) == 0) esc[buf][cl] = ldexpf(1.0f, -e);
       }
       elem* dst = &tile[buf][cl * LD + lrow];
+      typedef typename std::conditional<P == P_BF16, bf16x8, half8>::type vec8s;
+      vec8s pk;  // the 8 half-width values of this lane, one 16-byte LDS write
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         const double x = regs[r * 8 + i];
@@ -242,11 +244,13 @@ __global__ __launch_bounds__(SK_THREADS) void sketch_kernel(
           // compiler from fusing them into one float64 -> p conversion)
           float f = (float)ldexp(v, e);
           asm volatile("" : "+v"(f));
-          dst[i] = (elem)f;
+          if constexpr (KSTEP == 32) pk[i] = (elem)f;
+          else dst[i] = (elem)f;
         } else {
           dst[i] = v;
         }
       }
+      if constexpr (KSTEP == 32) *reinterpret_cast<vec8s*>(dst) = pk;
     }
     // 2. prefetch the next panel
     if (p + 1 < npanels) {
