@@ -50,13 +50,23 @@ extern "C" {
  * Selection": half for kappa < 1e4, single below 1e8, double otherwise).
  * BF16 is an extra option (8-bit exponent, 8-bit significand).
  * AUTO starts at FP16 and escalates per call from an on-device condition
- * estimate of Rs (see mrcqr_factor). */
+ * estimate of Rs (see mrcqr_factor).
+ * AUTO_CARRY is AUTO for a sequence of similar matrices (block Arnoldi,
+ * power iterations: Section "Adaptive Precision Selection", repeated
+ * calls): a call starts from the precision that the previous AUTO_CARRY
+ * call on the same workspace accepted, instead of from FP16, and escalates
+ * from there as AUTO does. The record lives in the workspace on the device,
+ * so it also carries across the replays of a captured graph; it never moves
+ * down (mrcqr_regime_reset forgets it). A workspace without a record (all
+ * zero bytes, as mrcqr_factor's own cached workspaces start) starts from
+ * FP16. Calls sharing one workspace share its record. */
 enum mrcqr_precision {
   MRCQR_PREC_AUTO = 0,
   MRCQR_PREC_FP64 = 1,
   MRCQR_PREC_FP32 = 2,
   MRCQR_PREC_FP16 = 3,
-  MRCQR_PREC_BF16 = 4
+  MRCQR_PREC_BF16 = 4,
+  MRCQR_PREC_AUTO_CARRY = 5
 };
 
 enum mrcqr_status {
@@ -117,6 +127,14 @@ int mrcqr_execute(const mrcqr_plan* plan, void* workspace, size_t workspace_byte
                   double* Q, int64_t ldq, double* R, int64_t ldr,
                   void* stream, mrcqr_info* info_dev);
 int mrcqr_plan_destroy(mrcqr_plan* plan);
+
+/* Forget the AUTO_CARRY record of a workspace (Section "Adaptive Precision
+ * Selection", repeated calls): the next AUTO_CARRY call on it starts from
+ * FP16 again. Enqueued on `stream` as one small kernel (no memset, so it may
+ * be captured). workspace: the plan's workspace, at least
+ * mrcqr_plan_workspace_bytes bytes. Returns MRCQR_ERR_ARG for a NULL plan
+ * and MRCQR_ERR_WORKSPACE for a missing or short workspace. */
+int mrcqr_regime_reset(const mrcqr_plan* plan, void* workspace, size_t workspace_bytes, void* stream);
 
 /* Many independent factorizations (e.g. the repeated QRs of block Arnoldi
  * or randomized SVD power steps). Per-instance arrays are HOST arrays of

@@ -23,7 +23,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmrcqr.so")
 
-PREC = {"auto": 0, "fp64": 1, "fp32": 2, "fp16": 3, "bf16": 4}
+PREC = {"auto": 0, "fp64": 1, "fp32": 2, "fp16": 3, "bf16": 4, "auto_carry": 5}
 PREC_NAME = {v: k for k, v in PREC.items()}
 STATUS = {
     0: "ok", 1: "invalid argument", 2: "non-finite sketch", 3: "cholesky breakdown",
@@ -68,6 +68,7 @@ def lib() -> ctypes.CDLL:
             "mrcqr_tri_inverse": (i32, [vp, i64, i64, vp, i64, vp]),
             "mrcqr_form_q": (i32, [vp, i64, i64, i64, vp, i64, vp, i64, vp]),
             "mrcqr_condest": (i32, [vp, i64, i64, vp, vp]),
+            "mrcqr_regime_reset": (i32, [vp, vp, sz, vp]),
             "mrcqr_status_string": (ctypes.c_char_p, [i32]),
             "mrcqr_version": (i32, []),
         }
@@ -177,13 +178,19 @@ class Plan:
         self._p = p
         self.m, self.n = m, n
         self.workspace_bytes = int(lib().mrcqr_plan_workspace_bytes(p))
-        self.workspace = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=device)
+        # zero bytes: no AUTO_CARRY record, so the first carrying call starts from FP16
+        self.workspace = torch.zeros(self.workspace_bytes, dtype=torch.uint8, device=device)
         self.info = torch.empty(INFO_BYTES, dtype=torch.uint8, device=device)
 
     def execute(self, A, Q, R, precision="fp16", seed: int = 0, stream=None):
         _check(lib().mrcqr_execute(self._p, self.workspace.data_ptr(), self.workspace_bytes, A.data_ptr(), _ld(A),
                                    _prec(precision), seed & (2 ** 64 - 1), Q.data_ptr(), _ld(Q), R.data_ptr(),
                                    _ld(R), _stream(stream), self.info.data_ptr()), "mrcqr_execute")
+
+    def reset_regime(self, stream=None):
+        """Forget the precision carried by 'auto_carry' calls on this plan."""
+        _check(lib().mrcqr_regime_reset(self._p, self.workspace.data_ptr(), self.workspace_bytes,
+                                        _stream(stream)), "mrcqr_regime_reset")
 
     def last_info(self) -> Info:
         return read_infos(self.info)[0]

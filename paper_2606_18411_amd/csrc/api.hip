@@ -8,6 +8,7 @@
 #include "mrcqr.h"
 
 namespace mrcqr {
+hipError_t launch_regime_reset(Ctrl* ctrl, hipStream_t st);
 hipError_t launch_draw(uint64_t seed, int m, int s, int32_t* S, int8_t* D, hipStream_t st, Ctrl* ctrl = nullptr,
                        int prec = 0, int auto_mode = 0);
 hipError_t launch_sketch(int prec, const double* A, int64_t lda, int m, int n, const int32_t* S, int s,
@@ -48,7 +49,7 @@ constexpr int64_t MMAX = (int64_t)1 << 28;
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 bool valid_prec(int p, bool allow_auto) {
-  return (allow_auto && p == MRCQR_PREC_AUTO) || p == MRCQR_PREC_FP64 || p == MRCQR_PREC_FP32 ||
+  return (allow_auto && (p == MRCQR_PREC_AUTO || p == MRCQR_PREC_AUTO_CARRY)) || p == MRCQR_PREC_FP64 || p == MRCQR_PREC_FP32 ||
          p == MRCQR_PREC_FP16 || p == MRCQR_PREC_BF16;
 }
 
@@ -105,8 +106,9 @@ static int execute(const mrcqr_plan* p, char* ws, const double* A, int64_t lda, 
   void* Tw = ws + p->off_Tw;
   const int64_t ldb = p->m;
   hipError_t e;
-  const bool automode = prec == MRCQR_PREC_AUTO;
-  if ((e = launch_draw(seed, m, s, S, nullptr, st, ctrl, automode ? P_FP16 : prec, automode ? 1 : 0)) != hipSuccess)
+  const bool automode = prec == MRCQR_PREC_AUTO || prec == MRCQR_PREC_AUTO_CARRY;
+  const int amode = prec == MRCQR_PREC_AUTO_CARRY ? AM_CARRY : automode ? AM_AUTO : AM_FIXED;
+  if ((e = launch_draw(seed, m, s, S, nullptr, st, ctrl, automode ? P_FP16 : prec, amode)) != hipSuccess)
     return MRCQR_ERR_DEVICE;
   // The launch sequence is static: in AUTO every attempt is enqueued and
   // the kernels of an attempt whose precision is not the current one (or of
@@ -188,6 +190,13 @@ int mrcqr_execute(const mrcqr_plan* plan, void* workspace, size_t workspace_byte
                  as_stream(stream), info_dev);
 }
 
+int mrcqr_regime_reset(const mrcqr_plan* plan, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!plan) return MRCQR_ERR_ARG;
+  if (!workspace || workspace_bytes < plan->total) return MRCQR_ERR_WORKSPACE;
+  Ctrl* ctrl = reinterpret_cast<Ctrl*>(static_cast<char*>(workspace) + plan->off_ctrl);
+  return hip_status(launch_regime_reset(ctrl, as_stream(stream)));
+}
+
 int mrcqr_factor(const double* A, int64_t m, int64_t n, int64_t lda, int sketch_precision, uint64_t seed,
                  int64_t s, double* Q, int64_t ldq, double* R, int64_t ldr, void* stream, mrcqr_info* info_dev) {
   if (s == 0) s = 2 * n;
@@ -205,6 +214,11 @@ int mrcqr_factor(const double* A, int64_t m, int64_t n, int64_t lda, int sketch_
       ce.plan.m = m; ce.plan.n = n; ce.plan.s = s;
       plan_layout(&ce.plan);
       if (hipMalloc(&ce.ws, ce.plan.total) != hipSuccess) return MRCQR_ERR_DEVICE;
+      // no AUTO_CARRY record yet: the control block starts as zero bytes
+      if (hipMemset(ce.ws, 0, sizeof(Ctrl)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        (void)hipFree(ce.ws);
+        return MRCQR_ERR_DEVICE;
+      }
       it = g_cache.emplace(key, ce).first;
     }
     ent = &it->second;

@@ -173,9 +173,12 @@ __global__ __launch_bounds__(CH_THREADS) void chol_kernel(
           ctrl->retry = 1;
           ctrl->cur_prec = (p == P_FP16) ? P_FP32 : P_FP64;
           ctrl->escalations += 1;
-        } else if (ctrl->status == ST_OK) {
-          if (f >= 0) { ctrl->status = ST_CHOL; ctrl->chol_fail = f; }
-          else if (!(kappa <= TAU_POSTERIOR)) ctrl->status = ST_POSTERIOR;
+        } else {
+          if (ctrl->status == ST_OK) {
+            if (f >= 0) { ctrl->status = ST_CHOL; ctrl->chol_fail = f; }
+            else if (!(kappa <= TAU_POSTERIOR)) ctrl->status = ST_POSTERIOR;
+          }
+          ctrl_carry_record(ctrl);
         }
       }
     }

@@ -67,12 +67,20 @@ struct Ctrl {
   int32_t status;       // mrcqr_status so far
   int32_t chol_fail;    // first failing Cholesky pivot or -1
   int32_t escalations;  // AUTO escalations
-  int32_t auto_mode;    // 1 when the precision is chosen on the device
+  int32_t auto_mode;    // AutoMode: how the precision is chosen
   int32_t retry;        // 1 when the posterior check asked for a rerun
-  int32_t pad0, pad1;
+  int32_t carry_prec;   // precision the last carrying call accepted
+  int32_t pad0;
+  uint64_t carry_tag;   // CARRY_TAG while carry_prec holds a record
   double kappa_rs;
   double kappa_rc;
 };
+
+// Precision choice of a call: fixed; AUTO from FP16; AUTO from the
+// precision the previous carrying call on this workspace accepted (repeated
+// calls on similar matrices, Section "Adaptive Precision Selection").
+enum AutoMode : int32_t { AM_FIXED = 0, AM_AUTO = 1, AM_CARRY = 2 };
+constexpr uint64_t CARRY_TAG = 0x4D52435152454731ull;
 
 // Status values (mirror of mrcqr_status in mrcqr.h).
 enum : int32_t {
@@ -88,9 +96,14 @@ constexpr double TAU_FP32 = 1e8;
 constexpr double TAU_BF16 = 1e2;
 constexpr double TAU_POSTERIOR = 20.0;
 
-// Start-of-call state of the control block (one thread writes it).
+// Start-of-call state of the control block (one thread writes it). The
+// carry record survives; a carrying call starts from it when it is valid.
 __device__ __forceinline__ void ctrl_reset(Ctrl* ctrl, int prec, int auto_mode) {
-  ctrl->cur_prec = prec;
+  int start = prec;
+  if (auto_mode == AM_CARRY && ctrl->carry_tag == CARRY_TAG &&
+      (ctrl->carry_prec == P_FP32 || ctrl->carry_prec == P_FP64))
+    start = ctrl->carry_prec;
+  ctrl->cur_prec = start;
   ctrl->status = ST_OK;
   ctrl->chol_fail = -1;
   ctrl->escalations = 0;
@@ -98,6 +111,15 @@ __device__ __forceinline__ void ctrl_reset(Ctrl* ctrl, int prec, int auto_mode) 
   ctrl->retry = 0;
   ctrl->kappa_rs = 0.0;
   ctrl->kappa_rc = 0.0;
+}
+
+// Called once the call's precision is final: a carrying call leaves it as
+// the start of the next one.
+__device__ __forceinline__ void ctrl_carry_record(Ctrl* ctrl) {
+  if (ctrl->auto_mode == AM_CARRY) {
+    ctrl->carry_prec = ctrl->cur_prec;
+    ctrl->carry_tag = CARRY_TAG;
+  }
 }
 
 // Launch gating of the static launch sequence (no host round trip):

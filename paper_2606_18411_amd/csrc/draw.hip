@@ -118,6 +118,19 @@ __global__ void signs_kernel(uint64_t seed, int m, int8_t* D) {
     D[t] = (hash_at(key0, (uint64_t)t) >> 63) ? (int8_t)-1 : (int8_t)1;
 }
 
+// Forgets the carry record of a control block.
+__global__ void regime_reset_kernel(Ctrl* ctrl) {
+  if (threadIdx.x == 0) {
+    ctrl->carry_tag = 0;
+    ctrl->carry_prec = 0;
+  }
+}
+
+hipError_t launch_regime_reset(Ctrl* ctrl, hipStream_t st) {
+  hipLaunchKernelGGL(regime_reset_kernel, dim3(1), dim3(64), 0, st, ctrl);
+  return hipGetLastError();
+}
+
 hipError_t launch_draw(uint64_t seed, int m, int s, int32_t* S, int8_t* D, hipStream_t st, Ctrl* ctrl, int prec,
                        int auto_mode) {
   int P = 1;

@@ -19,6 +19,7 @@ from .matrices import (
     upper_triangular,
     spd_matrix,
     instance_mix,
+    rising_kappas,
 )
 
 __all__ = [
@@ -29,4 +30,5 @@ __all__ = [
     "upper_triangular",
     "spd_matrix",
     "instance_mix",
+    "rising_kappas",
 ]

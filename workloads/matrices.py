@@ -87,3 +87,12 @@ def instance_mix(count: int, seed: int, m_range=(4096, 131072), n_choices=(8, 16
     ns = rng.choice(np.asarray(n_choices), size=count)
     ks = np.power(10.0, rng.uniform(log_kappa_range[0], log_kappa_range[1], size=count))
     return [(int(a), int(b), float(c)) for a, b, c in zip(ms, ns, ks)]
+
+
+def rising_kappas(calls: int, lo_exp: float = 2.0, hi_exp: float = 14.0) -> np.ndarray:
+    """kappa_k = 10^(lo + (hi - lo) k / (calls - 1)), k = 0..calls-1: the
+    slowly worsening conditioning of a repeated-QR loop (block Krylov or
+    power steps), with the same U and V and only sigma changing per call."""
+    if calls == 1:
+        return np.array([10.0 ** lo_exp])
+    return 10.0 ** (lo_exp + (hi_exp - lo_exp) * np.arange(calls) / (calls - 1))
