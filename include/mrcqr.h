@@ -136,11 +136,50 @@ int mrcqr_plan_destroy(mrcqr_plan* plan);
  * and MRCQR_ERR_WORKSPACE for a missing or short workspace. */
 int mrcqr_regime_reset(const mrcqr_plan* plan, void* workspace, size_t workspace_bytes, void* stream);
 
-/* Many independent factorizations (e.g. the repeated QRs of block Arnoldi
- * or randomized SVD power steps). Per-instance arrays are HOST arrays of
- * length `batch`; the matrices they point to are device memory. seeds[i]
- * selects instance i's draw. infos_dev: device array of `batch` infos (or
- * NULL). All instances are enqueued on `stream`. */
+/* ---------------------------------------------------------------------
+ * Batches of independent factorizations of uneven shapes (the repeated QRs
+ * of block Arnoldi or randomized-SVD power steps; each member is Algorithm 2
+ * with s = 2 n). Each step of Algorithm 2 runs as one launch over every
+ * member (one per kernel configuration: members are grouped by the size
+ * class of n), grid (blocks per member, members), instead of one launch per
+ * member and step; every member follows its own precision policy, AUTO
+ * escalation and posterior rerun on the device. Member i's Q and R are
+ * bitwise those of mrcqr_factor on the same A, policy and seed.
+ * ------------------------------------------------------------------- */
+typedef struct mrcqr_batch_plan mrcqr_batch_plan;
+
+/* Plan for `batch` members (1 <= batch <= 65535) of shapes m[i] x n[i]
+ * (HOST arrays); each shape must be valid for mrcqr_factor with s = 2 n[i].
+ * The plan owns small device tables (hipMalloc at creation). Returns
+ * MRCQR_ERR_ARG / MRCQR_ERR_UNSUPPORTED for a bad shape. */
+int mrcqr_batch_plan_create(int32_t batch, const int64_t* m, const int64_t* n, mrcqr_batch_plan** out);
+/* Workspace for one execution: the members' single-call workspaces side by
+ * side (about 2 m n 8 bytes per member plus partial sums). */
+size_t mrcqr_batch_plan_workspace_bytes(const mrcqr_batch_plan* plan);
+int mrcqr_batch_plan_destroy(mrcqr_batch_plan* plan);
+
+/* Enqueue the batch on `stream`; allocates nothing, launches a fixed
+ * sequence (graph-capturable). Every per-member array is a DEVICE array of
+ * length batch: A[i], Q[i], R[i] are device pointers to member i's
+ * column-major matrices, lda/ldq/ldr its leading dimensions, precision[i]
+ * its mrcqr_precision policy, seeds[i] its draw. The host checks only that
+ * the arrays are non-NULL and the workspace size; the device checks every
+ * member's arguments (non-NULL, A != Q, lda >= m, ldq >= m, ldr >= n, a
+ * valid policy) and skips a member that fails, with status MRCQR_ERR_ARG in
+ * its info. infos_dev: device array of `batch` infos, or NULL. A workspace
+ * of zero bytes holds no AUTO_CARRY records. */
+int mrcqr_batch_execute(const mrcqr_batch_plan* plan, void* workspace, size_t workspace_bytes,
+                        const double* const* A, const int64_t* lda, const int32_t* precision,
+                        const uint64_t* seeds, double* const* Q, const int64_t* ldq,
+                        double* const* R, const int64_t* ldr, void* stream, mrcqr_info* infos_dev);
+
+/* The same with HOST per-member arrays (the matrices are device memory),
+ * checked synchronously like mrcqr_factor. A batch plan, its workspace
+ * (zeroed when created) and the argument arrays are cached per device and
+ * shape list; the arrays are copied to the device with a blocking copy, after
+ * the previous call with the same shape list has finished reading them.
+ * Not for graph capture (use mrcqr_batch_execute). infos_dev: device array
+ * of `batch` infos (or NULL). */
 int mrcqr_factor_batched(int32_t batch, const double* const* A, const int64_t* m,
                          const int64_t* n, const int64_t* lda, const int32_t* precision,
                          const uint64_t* seeds, double* const* Q, const int64_t* ldq,

@@ -69,6 +69,10 @@ def lib() -> ctypes.CDLL:
             "mrcqr_form_q": (i32, [vp, i64, i64, i64, vp, i64, vp, i64, vp]),
             "mrcqr_condest": (i32, [vp, i64, i64, vp, vp]),
             "mrcqr_regime_reset": (i32, [vp, vp, sz, vp]),
+            "mrcqr_batch_plan_create": (i32, [i32, vp, vp, ctypes.POINTER(vp)]),
+            "mrcqr_batch_plan_workspace_bytes": (sz, [vp]),
+            "mrcqr_batch_plan_destroy": (i32, [vp]),
+            "mrcqr_batch_execute": (i32, [vp, vp, sz, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]),
             "mrcqr_status_string": (ctypes.c_char_p, [i32]),
             "mrcqr_version": (i32, []),
         }
@@ -199,6 +203,58 @@ class Plan:
         try:
             if getattr(self, "_p", None) is not None and _lib is not None:
                 _lib.mrcqr_plan_destroy(self._p)
+        except Exception:
+            pass
+
+
+class BatchPlan:
+    """A batch of independent factorizations of shapes [(m, n), ...] (s = 2n),
+    run as grouped launches; execute() allocates nothing once the per-member
+    argument arrays (device tensors) are set with bind()."""
+
+    def __init__(self, shapes, device="cuda"):
+        k = len(shapes)
+        ms = (ctypes.c_int64 * k)(*[int(m) for m, _ in shapes])
+        ns = (ctypes.c_int64 * k)(*[int(n) for _, n in shapes])
+        p = ctypes.c_void_p()
+        _check(lib().mrcqr_batch_plan_create(k, ms, ns, ctypes.byref(p)), "mrcqr_batch_plan_create")
+        self._p = p
+        self.shapes = [(int(m), int(n)) for m, n in shapes]
+        self.device = device
+        self.workspace_bytes = int(lib().mrcqr_batch_plan_workspace_bytes(p))
+        # zero bytes: no AUTO_CARRY records
+        self.workspace = torch.zeros(self.workspace_bytes, dtype=torch.uint8, device=device)
+        self.infos = torch.empty(INFO_BYTES * k, dtype=torch.uint8, device=device)
+        self._args = None
+
+    def bind(self, As, Qs, Rs, precisions, seeds):
+        """Per-member arguments as device arrays (kept alive by the plan)."""
+        dev = self.device
+        i64 = lambda vals: torch.tensor(vals, dtype=torch.int64, device=dev)
+        precs = precisions if isinstance(precisions, (list, tuple)) else [precisions] * len(As)
+        self._args = (
+            i64([a.data_ptr() for a in As]), i64([_ld(a) for a in As]),
+            torch.tensor([_prec(q) for q in precs], dtype=torch.int32, device=dev),
+            i64([int(x) & (2 ** 63 - 1) if int(x) < 2 ** 63 else int(x) - 2 ** 64 for x in seeds]),
+            i64([q.data_ptr() for q in Qs]), i64([_ld(q) for q in Qs]),
+            i64([r.data_ptr() for r in Rs]), i64([_ld(r) for r in Rs]),
+            (As, Qs, Rs),
+        )
+
+    def execute(self, stream=None, infos=True):
+        a = self._args
+        _check(lib().mrcqr_batch_execute(self._p, self.workspace.data_ptr(), self.workspace_bytes, a[0].data_ptr(),
+                                         a[1].data_ptr(), a[2].data_ptr(), a[3].data_ptr(), a[4].data_ptr(),
+                                         a[5].data_ptr(), a[6].data_ptr(), a[7].data_ptr(), _stream(stream),
+                                         self.infos.data_ptr() if infos else None), "mrcqr_batch_execute")
+
+    def last_infos(self):
+        return read_infos(self.infos, len(self.shapes))
+
+    def __del__(self):
+        try:
+            if getattr(self, "_p", None) is not None and _lib is not None:
+                _lib.mrcqr_batch_plan_destroy(self._p)
         except Exception:
             pass
 

@@ -1,10 +1,13 @@
 // Host side of the C ABI (include/mrcqr.h): argument checks, plans and
 // workspace layout, and the launch sequence of Algorithm 2.
+#include <algorithm>
+#include <cstring>
 #include <map>
+#include <vector>
 #include <mutex>
 #include <tuple>
 
-#include "common.hpp"
+#include "batch.hpp"
 #include "mrcqr.h"
 
 namespace mrcqr {
@@ -36,6 +39,34 @@ hipError_t launch_rc_tail(const double* Rc, int n, int64_t ldc, const double* Rs
 hipError_t launch_qform(const double* B, int m, int n, int64_t ldb, const double* X, int64_t ldx, double* Q,
                         int64_t ldq, const Ctrl* ctrl, int phase, hipStream_t st);
 hipError_t launch_ctrl_finalize(const Ctrl* ctrl, void* info, hipStream_t st);
+// grouped launches over the members of a batch
+hipError_t launch_draw_grouped(const BatchInst* bi, const int32_t* members, int count, int max_s,
+                               const BatchCall& call, hipStream_t st);
+bool sketch_full_tiles(int n, int s);
+hipError_t launch_sketch_grouped(int prec, bool full, const BatchInst* bi, const int32_t* members, int count,
+                                 int max_chunks, int64_t max_ns, const BatchCall& call, int phase, hipStream_t st);
+int qr_group_key(bool f64, int s, int n);
+hipError_t launch_sketch_qr_grouped(bool f64, int key, const BatchInst* bi, const int32_t* members, int count,
+                                    int max_n, const BatchCall& call, int slot, int phase, hipStream_t st);
+int trsm_batch_blocks(int64_t m);
+int trsm_prep_elems(int n);
+hipError_t launch_trsm_grouped(int nmax, const BatchInst* bi, const int32_t* members, int count, int max_elems,
+                               int max_blocks, const BatchCall& call, int phase, hipStream_t st);
+int gram_batch_chunks(int64_t m);
+bool syrk_full_tiles(int n);
+hipError_t launch_gram_grouped(bool full, const BatchInst* bi, const int32_t* members, int count, int max_chunks,
+                               int max_n, const BatchCall& call, int phase, hipStream_t st);
+hipError_t launch_cholesky_grouped(const BatchInst* bi, const int32_t* members, int count, const BatchCall& call,
+                                   int phase, hipStream_t st);
+hipError_t launch_rc_tail_grouped(const BatchInst* bi, const int32_t* members, int count, int max_n,
+                                  const BatchCall& call, int phase, hipStream_t st);
+int qform_batch_blocks(int64_t m);
+hipError_t launch_qform_grouped(int nb, const BatchInst* bi, const int32_t* members, int count, int max_blocks,
+                                const BatchCall& call, int phase, hipStream_t st);
+hipError_t launch_finalize_grouped(const BatchInst* bi, const int32_t* members, int count, const BatchCall& call,
+                                   hipStream_t st);
+struct SketchGeom { int chunks, rows_per_chunk; };
+SketchGeom sketch_geometry(int64_t m);
 }  // namespace mrcqr
 
 using namespace mrcqr;
@@ -151,11 +182,158 @@ static int check_factor_args(const double* A, int64_t m, int64_t n, int64_t lda,
   return MRCQR_OK;
 }
 
+// ---- batches: grouped launches (one per step and kernel configuration) ----
+struct BatchGroup {
+  int off = 0, count = 0, key = 0, max_a = 0, max_b = 0;
+};
+
+struct mrcqr_batch_plan {
+  int32_t batch = 0;
+  size_t total = 0;
+  BatchInst* d_inst = nullptr;
+  int32_t* d_members = nullptr;
+  BatchGroup all;
+  std::vector<BatchGroup> qr32, qr64, trsm, qform, sketch, gram;
+  int max_s = 0, max_n = 0;
+};
+
+static void batch_plan_free(mrcqr_batch_plan* p) {
+  if (!p) return;
+  if (p->d_inst) (void)hipFree(p->d_inst);
+  if (p->d_members) (void)hipFree(p->d_members);
+  delete p;
+}
+
+static int batch_plan_build(int32_t batch, const int64_t* m, const int64_t* n, mrcqr_batch_plan** out) {
+  if (!out || batch < 1 || !m || !n) return MRCQR_ERR_ARG;
+  if (batch > 65535) return MRCQR_ERR_UNSUPPORTED;  // members index grid.y
+  std::vector<BatchInst> inst(batch);
+  std::vector<int32_t> members;
+  std::map<int, std::vector<int32_t>> g32, g64, gtr, gqf, gsk, ggr;
+  mrcqr_batch_plan* p = new mrcqr_batch_plan();
+  p->batch = batch;
+  size_t o = 0;
+  for (int32_t i = 0; i < batch; ++i) {
+    const int64_t s = 2 * n[i];
+    const int c = check_shape(m[i], n[i], s);
+    if (c) { batch_plan_free(p); return c; }
+    mrcqr_plan pl;
+    pl.m = m[i]; pl.n = n[i]; pl.s = s;
+    plan_layout(&pl);
+    BatchInst& d = inst[i];
+    d.m = (int32_t)m[i]; d.n = (int32_t)n[i]; d.s = (int32_t)s;
+    const SketchGeom gg = sketch_geometry(m[i]);
+    d.sk_chunks = gg.chunks; d.sk_rows = gg.rows_per_chunk;
+    d.gram_chunks = gram_batch_chunks(m[i]);
+    d.trsm_blocks = trsm_batch_blocks(m[i]);
+    d.qform_blocks = qform_batch_blocks(m[i]);
+    d.ws = o;
+    d.off_ctrl = pl.off_ctrl; d.off_S = pl.off_S; d.off_Ypart = pl.off_Ypart; d.off_Y = pl.off_Y;
+    d.off_Rs = pl.off_Rs; d.off_Gpart = pl.off_Gpart; d.off_G = pl.off_G; d.off_Rc = pl.off_Rc;
+    d.off_Rci = pl.off_Rci; d.off_Tw = pl.off_Tw; d.off_B = pl.off_B;
+    o = align_up(o + pl.total);
+    const int k32 = qr_group_key(false, d.s, d.n), k64 = qr_group_key(true, d.s, d.n);
+    if (k32 < 0 || k64 < 0) { batch_plan_free(p); return MRCQR_ERR_UNSUPPORTED; }
+    g32[k32].push_back(i);
+    g64[k64].push_back(i);
+    gtr[d.n <= 32 ? 32 : (d.n <= 64 ? 64 : 128)].push_back(i);
+    gqf[(d.n + 15) / 16].push_back(i);
+    gsk[sketch_full_tiles(d.n, d.s) ? 1 : 0].push_back(i);
+    ggr[syrk_full_tiles(d.n) ? 1 : 0].push_back(i);
+    p->max_s = std::max(p->max_s, d.s);
+    p->max_n = std::max(p->max_n, d.n);
+  }
+  p->total = o;
+  p->all.off = 0;
+  p->all.count = batch;
+  for (int32_t i = 0; i < batch; ++i) members.push_back(i);
+  auto add_groups = [&](std::map<int, std::vector<int32_t>>& g, std::vector<BatchGroup>& dst, int kind) {
+    for (auto& kv : g) {
+      BatchGroup bg;
+      bg.off = (int)members.size();
+      bg.count = (int)kv.second.size();
+      bg.key = kv.first;
+      for (int32_t i : kv.second) {
+        members.push_back(i);
+        const BatchInst& d = inst[i];
+        if (kind == 0) bg.max_a = std::max(bg.max_a, d.n);                   // sketch QR: LDS for the largest n
+        if (kind == 1) { bg.max_a = std::max(bg.max_a, trsm_prep_elems(d.n)); bg.max_b = std::max(bg.max_b, d.trsm_blocks); }
+        if (kind == 2) bg.max_b = std::max(bg.max_b, d.qform_blocks);
+        if (kind == 3) { bg.max_a = std::max(bg.max_a, d.sk_chunks); bg.max_b = std::max(bg.max_b, d.n * d.s); }
+        if (kind == 4) { bg.max_a = std::max(bg.max_a, d.gram_chunks); bg.max_b = std::max(bg.max_b, d.n); }
+      }
+      dst.push_back(bg);
+    }
+  };
+  add_groups(g32, p->qr32, 0);
+  add_groups(g64, p->qr64, 0);
+  add_groups(gtr, p->trsm, 1);
+  add_groups(gqf, p->qform, 2);
+  add_groups(gsk, p->sketch, 3);
+  add_groups(ggr, p->gram, 4);
+  if (hipMalloc(&p->d_inst, inst.size() * sizeof(BatchInst)) != hipSuccess ||
+      hipMalloc(&p->d_members, members.size() * sizeof(int32_t)) != hipSuccess ||
+      hipMemcpy(p->d_inst, inst.data(), inst.size() * sizeof(BatchInst), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(p->d_members, members.data(), members.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
+    batch_plan_free(p);
+    return MRCQR_ERR_DEVICE;
+  }
+  *out = p;
+  return MRCQR_OK;
+}
+
+// The static launch sequence of the single factorization, each step as one
+// grouped launch per kernel configuration; every member follows its own
+// control block (precision, escalation, rerun) on the device.
+static int batch_execute(const mrcqr_batch_plan* p, const BatchCall& call, hipStream_t st) {
+  const BatchInst* bi = p->d_inst;
+  const int32_t* all = p->d_members + p->all.off;
+  const int nb = p->batch;
+  bool ok = launch_draw_grouped(bi, all, nb, p->max_s, call, st) == hipSuccess;
+  auto stage1 = [&](int pp, int phase) {
+    for (const BatchGroup& g : p->sketch)
+      ok = ok && launch_sketch_grouped(pp, g.key == 1, bi, p->d_members + g.off, g.count, g.max_a, g.max_b, call, phase,
+                                       st) == hipSuccess;
+    for (const BatchGroup& g : (pp == P_FP64 ? p->qr64 : p->qr32))
+      ok = ok && launch_sketch_qr_grouped(pp == P_FP64, g.key, bi, p->d_members + g.off, g.count, g.max_a, call, pp,
+                                          phase, st) == hipSuccess;
+  };
+  auto stage2 = [&](int phase, int tail) {
+    for (const BatchGroup& g : p->trsm)
+      ok = ok && launch_trsm_grouped(g.key, bi, p->d_members + g.off, g.count, g.max_a, g.max_b, call, phase, st) ==
+                     hipSuccess;
+    for (const BatchGroup& g : p->gram)
+      ok = ok && launch_gram_grouped(g.key == 1, bi, p->d_members + g.off, g.count, g.max_a, g.max_b, call, phase, st) ==
+                     hipSuccess;
+    ok = ok && launch_cholesky_grouped(bi, all, nb, call, phase, st) == hipSuccess;
+    ok = ok && launch_rc_tail_grouped(bi, all, nb, p->max_n, call, tail, st) == hipSuccess;
+    for (const BatchGroup& g : p->qform)
+      ok = ok && launch_qform_grouped(g.key, bi, p->d_members + g.off, g.count, g.max_b, call, tail, st) == hipSuccess;
+  };
+  for (int pp : {P_FP16, P_BF16, P_FP32, P_FP64}) stage1(pp, PH_FIRST);
+  stage2(PH_FIRST, PH_FIRST_TAIL);
+  for (int pp : {P_FP32, P_FP64}) stage1(pp, PH_RERUN);
+  stage2(PH_RERUN, PH_RERUN);
+  if (call.info) ok = ok && launch_finalize_grouped(bi, all, nb, call, st) == hipSuccess;
+  return ok ? MRCQR_OK : MRCQR_ERR_DEVICE;
+}
+
 // ---- plan cache for mrcqr_factor ----
 namespace {
 struct CacheEntry { mrcqr_plan plan; void* ws; };
 std::mutex g_mu;
 std::map<std::tuple<int, int64_t, int64_t, int64_t>, CacheEntry> g_cache;
+// mrcqr_factor_batched: plan, workspace and per-call argument arrays per
+// (device, shape list)
+struct BatchEntry {
+  mrcqr_batch_plan* plan = nullptr;
+  void* ws = nullptr;
+  void* params = nullptr;
+  hipEvent_t done = nullptr;
+  bool used = false;
+};
+std::mutex g_batch_mu;
+std::map<std::vector<int64_t>, BatchEntry> g_batch_cache;
 }  // namespace
 
 extern "C" {
@@ -227,21 +405,86 @@ int mrcqr_factor(const double* A, int64_t m, int64_t n, int64_t lda, int sketch_
                  as_stream(stream), info_dev);
 }
 
+int mrcqr_batch_plan_create(int32_t batch, const int64_t* m, const int64_t* n, mrcqr_batch_plan** out) {
+  return batch_plan_build(batch, m, n, out);
+}
+
+size_t mrcqr_batch_plan_workspace_bytes(const mrcqr_batch_plan* plan) { return plan ? plan->total : 0; }
+
+int mrcqr_batch_plan_destroy(mrcqr_batch_plan* plan) {
+  batch_plan_free(plan);
+  return MRCQR_OK;
+}
+
+int mrcqr_batch_execute(const mrcqr_batch_plan* plan, void* workspace, size_t workspace_bytes,
+                        const double* const* A, const int64_t* lda, const int32_t* precision, const uint64_t* seeds,
+                        double* const* Q, const int64_t* ldq, double* const* R, const int64_t* ldr, void* stream,
+                        mrcqr_info* infos_dev) {
+  if (!plan || !A || !lda || !precision || !seeds || !Q || !ldq || !R || !ldr) return MRCQR_ERR_ARG;
+  if (!workspace || workspace_bytes < plan->total) return MRCQR_ERR_WORKSPACE;
+  BatchCall call{static_cast<char*>(workspace), A, lda, Q, ldq, R, ldr, precision, seeds, infos_dev};
+  return batch_execute(plan, call, as_stream(stream));
+}
+
 int mrcqr_factor_batched(int32_t batch, const double* const* A, const int64_t* m, const int64_t* n,
                          const int64_t* lda, const int32_t* precision, const uint64_t* seeds,
                          double* const* Q, const int64_t* ldq, double* const* R, const int64_t* ldr,
                          void* stream, mrcqr_info* infos_dev) {
   if (batch < 0 || (batch > 0 && (!A || !m || !n || !lda || !precision || !seeds || !Q || !ldq || !R || !ldr)))
     return MRCQR_ERR_ARG;
+  if (batch == 0) return MRCQR_OK;
   for (int32_t i = 0; i < batch; ++i) {
     const int c = check_factor_args(A[i], m[i], n[i], lda[i], precision[i], 2 * n[i], Q[i], ldq[i], R[i], ldr[i]);
     if (c) return c;
   }
-  for (int32_t i = 0; i < batch; ++i) {
-    const int c = mrcqr_factor(A[i], m[i], n[i], lda[i], precision[i], seeds[i], 0, Q[i], ldq[i], R[i], ldr[i],
-                               stream, infos_dev ? infos_dev + i : nullptr);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return MRCQR_ERR_DEVICE;
+  std::vector<int64_t> key{dev};
+  for (int32_t i = 0; i < batch; ++i) { key.push_back(m[i]); key.push_back(n[i]); }
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  auto it = g_batch_cache.find(key);
+  if (it == g_batch_cache.end()) {
+    BatchEntry be;
+    const int c = batch_plan_build(batch, m, n, &be.plan);
     if (c) return c;
+    const size_t pbytes = (size_t)batch * (6 * sizeof(int64_t) + sizeof(int32_t) + sizeof(uint64_t)) + 256;
+    if (hipMalloc(&be.ws, be.plan->total) != hipSuccess || hipMalloc(&be.params, pbytes) != hipSuccess ||
+        hipEventCreateWithFlags(&be.done, hipEventDisableTiming) != hipSuccess) {
+      batch_plan_free(be.plan);
+      return MRCQR_ERR_DEVICE;
+    }
+    // no AUTO_CARRY records yet
+    if (hipMemset(be.ws, 0, be.plan->total) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+      return MRCQR_ERR_DEVICE;
+    it = g_batch_cache.emplace(key, be).first;
   }
+  BatchEntry& be = it->second;
+  // the per-call arrays go to device memory; the previous call on this
+  // entry must be done reading them
+  if (be.used && hipEventSynchronize(be.done) != hipSuccess) return MRCQR_ERR_DEVICE;
+  std::vector<unsigned char> host((size_t)batch * (6 * sizeof(int64_t) + sizeof(int32_t) + sizeof(uint64_t)));
+  unsigned char* h = host.data();
+  const size_t b8 = (size_t)batch * 8;
+  std::memcpy(h, A, b8);
+  std::memcpy(h + b8, lda, b8);
+  std::memcpy(h + 2 * b8, Q, b8);
+  std::memcpy(h + 3 * b8, ldq, b8);
+  std::memcpy(h + 4 * b8, R, b8);
+  std::memcpy(h + 5 * b8, ldr, b8);
+  std::memcpy(h + 6 * b8, seeds, b8);
+  std::memcpy(h + 7 * b8, precision, (size_t)batch * sizeof(int32_t));
+  if (hipMemcpy(be.params, host.data(), host.size(), hipMemcpyHostToDevice) != hipSuccess) return MRCQR_ERR_DEVICE;
+  unsigned char* d = static_cast<unsigned char*>(be.params);
+  BatchCall call{static_cast<char*>(be.ws),
+                 reinterpret_cast<const double* const*>(d), reinterpret_cast<const int64_t*>(d + b8),
+                 reinterpret_cast<double* const*>(d + 2 * b8), reinterpret_cast<const int64_t*>(d + 3 * b8),
+                 reinterpret_cast<double* const*>(d + 4 * b8), reinterpret_cast<const int64_t*>(d + 5 * b8),
+                 reinterpret_cast<const int32_t*>(d + 7 * b8), reinterpret_cast<const uint64_t*>(d + 6 * b8),
+                 infos_dev};
+  const int c = batch_execute(be.plan, call, as_stream(stream));
+  if (c) return c;
+  if (hipEventRecord(be.done, as_stream(stream)) != hipSuccess) return MRCQR_ERR_DEVICE;
+  be.used = true;
   return MRCQR_OK;
 }
 

@@ -5,7 +5,7 @@
 // "Adaptive Precision Selection": an underestimated precision shows up as
 // lost orthogonality), Stage 3's product R = Rc Rs, and the small
 // per-call control kernels.
-#include "common.hpp"
+#include "batch.hpp"
 #include "ice.hpp"
 #include "small.hpp"
 
@@ -27,7 +27,7 @@ constexpr int CH_NMAX = 128;
 // Each entry ends as the textbook R[j][k] = (G[j][k] - sum_{i<j} R[i][j]
 // R[i][k]) / R[j][j], summed in another order. A pivot that is not
 // positive and finite stops the factorization (its index is reported).
-__global__ __launch_bounds__(CH_THREADS) void chol_kernel(
+__device__ __forceinline__ void chol_body(
     const double* __restrict__ G, int n, int64_t ldg, double* __restrict__ Rc, int64_t ldr,
     int32_t* __restrict__ fail_out, double* __restrict__ kappa_out, Ctrl* __restrict__ ctrl, int phase) {
   if (skip_launch(ctrl, P_AUTO, phase)) return;
@@ -185,6 +185,22 @@ __global__ __launch_bounds__(CH_THREADS) void chol_kernel(
   }
 }
 
+__global__ __launch_bounds__(CH_THREADS) void chol_kernel(
+    const double* __restrict__ G, int n, int64_t ldg, double* __restrict__ Rc, int64_t ldr,
+    int32_t* __restrict__ fail_out, double* __restrict__ kappa_out, Ctrl* __restrict__ ctrl, int phase) {
+  chol_body(G, n, ldg, Rc, ldr, fail_out, kappa_out, ctrl, phase);
+}
+
+// Grouped: one workgroup per member.
+__global__ __launch_bounds__(CH_THREADS) void chol_grouped(const BatchInst* __restrict__ bi,
+                                                           const int32_t* __restrict__ members, BatchCall call,
+                                                           int phase) {
+  const int i = bat_index(members);
+  const BatchInst& d = bi[i];
+  chol_body(bat_ptr<const double>(call, d, d.off_G), d.n, d.n, bat_ptr<double>(call, d, d.off_Rc), d.n, nullptr,
+            nullptr, bat_ptr<Ctrl>(call, d, d.off_ctrl), phase);
+}
+
 // Stage 3, stand-alone: R = R2 R1 (see trmm_tile).
 __global__ __launch_bounds__(64) void trmm_kernel(const double* __restrict__ R2, int64_t ld2,
                                                   const double* __restrict__ R1, int64_t ld1, int n,
@@ -212,6 +228,34 @@ __global__ void ctrl_finalize_kernel(const Ctrl* ctrl, InfoOut* info) {
 }
 
 
+
+__global__ void ctrl_finalize_grouped(const BatchInst* __restrict__ bi, const int32_t* __restrict__ members,
+                                      BatchCall call) {
+  const int i = bat_index(members);
+  const BatchInst& d = bi[i];
+  if (threadIdx.x == 0 && call.info) {
+    const Ctrl* ctrl = bat_ptr<const Ctrl>(call, d, d.off_ctrl);
+    InfoOut* info = reinterpret_cast<InfoOut*>(call.info) + i;
+    info->status = ctrl->status;
+    info->precision_used = ctrl->cur_prec;
+    info->chol_fail_index = ctrl->chol_fail;
+    info->escalations = ctrl->escalations;
+    info->kappa_rs_est = ctrl->kappa_rs;
+    info->kappa_rc_est = ctrl->kappa_rc;
+  }
+}
+
+hipError_t launch_cholesky_grouped(const BatchInst* bi, const int32_t* members, int count, const BatchCall& call,
+                                   int phase, hipStream_t st) {
+  hipLaunchKernelGGL(chol_grouped, dim3(1, count), dim3(CH_THREADS), 0, st, bi, members, call, phase);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_grouped(const BatchInst* bi, const int32_t* members, int count, const BatchCall& call,
+                                   hipStream_t st) {
+  hipLaunchKernelGGL(ctrl_finalize_grouped, dim3(1, count), dim3(64), 0, st, bi, members, call);
+  return hipGetLastError();
+}
 
 hipError_t launch_cholesky(const double* G, int n, int64_t ldg, double* Rc, int64_t ldr, int32_t* fail,
                            double* kappa, Ctrl* ctrl, int phase, hipStream_t st) {

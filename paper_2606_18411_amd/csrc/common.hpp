@@ -84,7 +84,7 @@ constexpr uint64_t CARRY_TAG = 0x4D52435152454731ull;
 
 // Status values (mirror of mrcqr_status in mrcqr.h).
 enum : int32_t {
-  ST_OK = 0, ST_NONFINITE = 2, ST_CHOL = 3, ST_SINGULAR = 4, ST_POSTERIOR = 7
+  ST_OK = 0, ST_ARG = 1, ST_NONFINITE = 2, ST_CHOL = 3, ST_SINGULAR = 4, ST_POSTERIOR = 7
 };
 
 // Regime bounds on the condition estimate of Rs (Section "Adaptive
@@ -132,6 +132,7 @@ enum Phase : int { PH_FIRST = 0, PH_RERUN = 1, PH_FIRST_TAIL = 2 };
 
 __device__ __forceinline__ bool skip_launch(const Ctrl* ctrl, int slot_prec, int phase) {
   if (ctrl == nullptr) return false;
+  if (ctrl->status == ST_ARG) return true;  // a batch member with invalid arguments
   if (phase == PH_RERUN && !ctrl->retry) return true;
   if (phase == PH_FIRST_TAIL && ctrl->retry) return true;
   return slot_prec != P_AUTO && ctrl->cur_prec != slot_prec;

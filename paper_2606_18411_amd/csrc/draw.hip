@@ -6,7 +6,7 @@
 // collides and S = {r_j}; that case is detected after sorting (no two equal
 // neighbours) and needs no sequential pass. Otherwise one wave replays the
 // insertions in order, keeping the set in registers (membership by ballot).
-#include "common.hpp"
+#include "batch.hpp"
 
 namespace mrcqr {
 
@@ -62,8 +62,8 @@ __device__ void bitonic_sort(uint32_t* keys, int P) {
 
 // With a control block, thread 0 also resets it for a new factorization
 // (the first launch of the call).
-__global__ __launch_bounds__(DRAW_THREADS) void draw_kernel(uint64_t seed, int m, int s, int32_t* S_out,
-                                                            Ctrl* ctrl, int prec, int auto_mode) {
+__device__ __forceinline__ void draw_body(uint64_t seed, int m, int s, int32_t* S_out, Ctrl* ctrl, int prec,
+                                          int auto_mode) {
   if (ctrl && threadIdx.x == 0) ctrl_reset(ctrl, prec, auto_mode);
   __shared__ uint32_t keys[DRAW_SMAX];
   __shared__ int dup;
@@ -112,6 +112,32 @@ __global__ __launch_bounds__(DRAW_THREADS) void draw_kernel(uint64_t seed, int m
   for (int i = threadIdx.x; i < s; i += blockDim.x) S_out[i] = (int32_t)keys[i];
 }
 
+__global__ __launch_bounds__(DRAW_THREADS) void draw_kernel(uint64_t seed, int m, int s, int32_t* S_out,
+                                                            Ctrl* ctrl, int prec, int auto_mode) {
+  draw_body(seed, m, s, S_out, ctrl, prec, auto_mode);
+}
+
+// Grouped: one workgroup per instance; the instance's policy gives the
+// starting precision and the AUTO mode.
+__global__ __launch_bounds__(DRAW_THREADS) void draw_grouped(const BatchInst* __restrict__ bi,
+                                                             const int32_t* __restrict__ members, BatchCall call) {
+  const int i = bat_index(members);
+  const BatchInst& d = bi[i];
+  const int p = call.prec[i];
+  const bool am = p == P_AUTO || p == 5;
+  Ctrl* ctrl = bat_ptr<Ctrl>(call, d, d.off_ctrl);
+  draw_body(call.seed[i], d.m, d.s, bat_ptr<int32_t>(call, d, d.off_S), ctrl, am ? P_FP16 : p,
+            p == 5 ? AM_CARRY : am ? AM_AUTO : AM_FIXED);
+  // the per-call arguments live in device memory: checked here, and a
+  // member that fails is skipped by every later kernel of the batch
+  if (threadIdx.x == 0) {
+    const bool ok = call.A[i] != nullptr && call.Q[i] != nullptr && call.R[i] != nullptr &&
+                    call.A[i] != call.Q[i] && call.lda[i] >= d.m && call.ldq[i] >= d.m && call.ldr[i] >= d.n &&
+                    p >= 0 && p <= 5;
+    if (!ok) ctrl->status = ST_ARG;
+  }
+}
+
 __global__ void signs_kernel(uint64_t seed, int m, int8_t* D) {
   const uint64_t key0 = stream_key(seed, 0);
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < m; t += gridDim.x * blockDim.x)
@@ -128,6 +154,15 @@ __global__ void regime_reset_kernel(Ctrl* ctrl) {
 
 hipError_t launch_regime_reset(Ctrl* ctrl, hipStream_t st) {
   hipLaunchKernelGGL(regime_reset_kernel, dim3(1), dim3(64), 0, st, ctrl);
+  return hipGetLastError();
+}
+
+hipError_t launch_draw_grouped(const BatchInst* bi, const int32_t* members, int count, int max_s,
+                               const BatchCall& call, hipStream_t st) {
+  int P = 1;
+  while (P < max_s) P <<= 1;
+  const int threads = P <= DRAW_THREADS ? (P < 64 ? 64 : P) : DRAW_THREADS;
+  hipLaunchKernelGGL(draw_grouped, dim3(1, count), dim3(threads), 0, st, bi, members, call);
   return hipGetLastError();
 }
 

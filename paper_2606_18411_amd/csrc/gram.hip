@@ -5,7 +5,7 @@
 // and each wave accumulates its share of the upper tiles with float64 MFMA
 // 16x16x4. Per-chunk partials are summed in a second kernel in fixed order
 // (deterministic, no atomics).
-#include "common.hpp"
+#include "batch.hpp"
 
 namespace mrcqr {
 
@@ -39,7 +39,8 @@ __device__ __forceinline__ void gr_tile(int w, int u, int& I, int& J) {
 // c + 2 chunks, ... (the slabs the triangular solve's workgroup c writes, in
 // the same 256-row units) and reads them last-written first, so that its
 // first panels are still in the memory-side cache.
-__global__ __launch_bounds__(GR_THREADS) void syrk_kernel(
+template <bool FULL>
+__device__ __forceinline__ void syrk_body(
     const double* __restrict__ B, int m, int n, int64_t ldb, int chunks,
     double* __restrict__ Gpart, const Ctrl* __restrict__ ctrl, int phase) {
   __shared__ double tile[2][GR_NMAX * GR_LDR];
@@ -67,6 +68,12 @@ __global__ __launch_bounds__(GR_THREADS) void syrk_kernel(
     has[u] = ti[u] < nb && tj[u] < nb;
     if (!has[u]) { ti[u] = 0; tj[u] = 0; }
   }
+  // FULL: all 8 x 8 block columns exist (n > 112). Otherwise the products of
+  // tiles that do not exist are skipped (their accumulators are never
+  // stored), and a wave without tiles skips the K loop.
+  bool any = FULL;
+#pragma unroll
+  for (int u = 0; u < GR_TPW; ++u) any = any || has[u];
   f64x4 acc[GR_TPW];
 #pragma unroll
   for (int u = 0; u < GR_TPW; ++u) acc[u] = f64x4{0, 0, 0, 0};
@@ -98,7 +105,9 @@ __global__ __launch_bounds__(GR_THREADS) void syrk_kernel(
     const double* tb = tile[buf] + c16 * GR_LDR + g;
     // no branches in the K loop: a tile that does not exist (beyond nb)
     // reads block 0 and its accumulator is never stored
-    if (w < 4) {
+    if (!any) {
+      // no tile of this wave exists
+    } else if (w < 4) {
       // one block row: one A operand, B operands of blocks p..p+4
 #pragma unroll 4
       for (int kk = 0; kk < GR_PANEL / 4; ++kk) {
@@ -108,7 +117,8 @@ __global__ __launch_bounds__(GR_THREADS) void syrk_kernel(
         for (int u = 0; u < GR_TPW; ++u) bo[u] = tk[16 * tj[u] * GR_LDR];
         const double a = tk[16 * ti[0] * GR_LDR];
 #pragma unroll
-        for (int u = 0; u < GR_TPW; ++u) acc[u] = mfma_f64(a, bo[u], acc[u]);
+        for (int u = 0; u < GR_TPW; ++u)
+          if (FULL || has[u]) acc[u] = mfma_f64(a, bo[u], acc[u]);
       }
     } else {
 #pragma unroll 4
@@ -121,7 +131,8 @@ __global__ __launch_bounds__(GR_THREADS) void syrk_kernel(
           bo[u] = tk[16 * tj[u] * GR_LDR];
         }
 #pragma unroll
-        for (int u = 0; u < GR_TPW - 1; ++u) acc[u] = mfma_f64(ao[u], bo[u], acc[u]);
+        for (int u = 0; u < GR_TPW - 1; ++u)
+          if (FULL || has[u]) acc[u] = mfma_f64(ao[u], bo[u], acc[u]);
       }
     }
   }
@@ -138,12 +149,37 @@ __global__ __launch_bounds__(GR_THREADS) void syrk_kernel(
   }
 }
 
+__global__ __launch_bounds__(GR_THREADS) void syrk_kernel(
+    const double* __restrict__ B, int m, int n, int64_t ldb, int chunks,
+    double* __restrict__ Gpart, const Ctrl* __restrict__ ctrl, int phase) {
+  syrk_body<true>(B, m, n, ldb, chunks, Gpart, ctrl, phase);
+}
+
+__global__ __launch_bounds__(GR_THREADS) void syrk_part_kernel(
+    const double* __restrict__ B, int m, int n, int64_t ldb, int chunks,
+    double* __restrict__ Gpart, const Ctrl* __restrict__ ctrl, int phase) {
+  syrk_body<false>(B, m, n, ldb, chunks, Gpart, ctrl, phase);
+}
+
+// Grouped: blockIdx.x is the member's chunk; members are grouped by the
+// variant a single call of their shape uses.
+template <bool FULL>
+__global__ __launch_bounds__(GR_THREADS) void syrk_grouped(const BatchInst* __restrict__ bi,
+                                                           const int32_t* __restrict__ members, BatchCall call,
+                                                           int phase) {
+  const int i = bat_index(members);
+  const BatchInst& d = bi[i];
+  if ((int)blockIdx.x >= d.gram_chunks) return;
+  syrk_body<FULL>(bat_ptr<const double>(call, d, d.off_B), d.m, d.n, d.m, d.gram_chunks,
+                  bat_ptr<double>(call, d, d.off_Gpart), bat_ptr<const Ctrl>(call, d, d.off_ctrl), phase);
+}
+
 // G[i, j] = G[j, i] = sum over chunks of the upper partial (i <= j). One
 // block per column j; its 4 waves sum 4 contiguous chunk ranges (lanes over
 // rows i), combined in LDS in fixed order (deterministic).
-__global__ __launch_bounds__(256) void gram_reduce_kernel(const double* __restrict__ Gpart, int chunks, int n,
-                                                          double* __restrict__ G, int64_t ldg,
-                                                          const Ctrl* __restrict__ ctrl, int phase) {
+__device__ __forceinline__ void gram_reduce_body(const double* __restrict__ Gpart, int chunks, int n,
+                                                 double* __restrict__ G, int64_t ldg,
+                                                 const Ctrl* __restrict__ ctrl, int phase) {
   if (skip_launch(ctrl, P_AUTO, phase)) return;
   __shared__ double part[4][64];
   const int j = blockIdx.x;
@@ -177,10 +213,38 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(const double* __restri
   }
 }
 
+__global__ __launch_bounds__(256) void gram_reduce_kernel(const double* __restrict__ Gpart, int chunks, int n,
+                                                          double* __restrict__ G, int64_t ldg,
+                                                          const Ctrl* __restrict__ ctrl, int phase) {
+  gram_reduce_body(Gpart, chunks, n, G, ldg, ctrl, phase);
+}
+
+__global__ __launch_bounds__(256) void gram_reduce_grouped(const BatchInst* __restrict__ bi,
+                                                           const int32_t* __restrict__ members, BatchCall call,
+                                                           int phase) {
+  const int i = bat_index(members);
+  const BatchInst& d = bi[i];
+  if ((int)blockIdx.x >= d.n) return;
+  gram_reduce_body(bat_ptr<const double>(call, d, d.off_Gpart), d.gram_chunks, d.n, bat_ptr<double>(call, d, d.off_G),
+                   d.n, bat_ptr<const Ctrl>(call, d, d.off_ctrl), phase);
+}
+
 // one workgroup per compute unit, at most one per slab
 static int gram_chunks(int64_t m) {
   const int64_t nslab = (m + GR_SLAB - 1) / GR_SLAB;
   return (int)(nslab < 256 ? nslab : 256);
+}
+
+int gram_batch_chunks(int64_t m) { return gram_chunks(m); }
+
+bool syrk_full_tiles(int n) { return n > GR_NMAX - 16; }
+
+hipError_t launch_gram_grouped(bool full, const BatchInst* bi, const int32_t* members, int count, int max_chunks,
+                               int max_n, const BatchCall& call, int phase, hipStream_t st) {
+  if (full) hipLaunchKernelGGL(syrk_grouped<true>, dim3(max_chunks, count), dim3(GR_THREADS), 0, st, bi, members, call, phase);
+  else hipLaunchKernelGGL(syrk_grouped<false>, dim3(max_chunks, count), dim3(GR_THREADS), 0, st, bi, members, call, phase);
+  hipLaunchKernelGGL(gram_reduce_grouped, dim3(max_n, count), dim3(256), 0, st, bi, members, call, phase);
+  return hipGetLastError();
 }
 
 size_t gram_partial_bytes(int64_t m, int64_t n) {
@@ -191,7 +255,11 @@ hipError_t launch_gram(const double* B, int m, int n, int64_t ldb, double* Gpart
                        const Ctrl* ctrl, int phase, hipStream_t st) {
   if (n > GR_NMAX) return hipErrorInvalidValue;
   const int chunks = gram_chunks(m);
-  hipLaunchKernelGGL(syrk_kernel, dim3(chunks), dim3(GR_THREADS), 0, st, B, m, n, ldb, chunks, Gpart, ctrl, phase);
+  if (syrk_full_tiles(n))  // every tile exists
+    hipLaunchKernelGGL(syrk_kernel, dim3(chunks), dim3(GR_THREADS), 0, st, B, m, n, ldb, chunks, Gpart, ctrl, phase);
+  else
+    hipLaunchKernelGGL(syrk_part_kernel, dim3(chunks), dim3(GR_THREADS), 0, st, B, m, n, ldb, chunks, Gpart, ctrl,
+                       phase);
   hipLaunchKernelGGL(gram_reduce_kernel, dim3(n), dim3(256), 0, st, (const double*)Gpart, chunks, n, G, ldg, ctrl, phase);
   return hipGetLastError();
 }

@@ -25,7 +25,7 @@
 // pairs (q, 4 NB - 1 - q), which cost the same NB + 1 MFMAs per tile
 // whatever q is, in chunks of 8 steps; up to three chunks ahead (of this
 // tile or the next) are loaded while one is multiplied.
-#include "common.hpp"
+#include "batch.hpp"
 #include "small.hpp"
 
 namespace mrcqr {
@@ -48,13 +48,12 @@ __global__ __launch_bounds__(64) void trinv_kernel(const double* __restrict__ R,
 // The small steps after the Cholesky of the factorization in one launch:
 // workgroups 0..n-1 form the columns of Rc^{-1} for Q, the rest the tiles of
 // Stage 3's R = Rc Rs (independent of each other).
-__global__ __launch_bounds__(64) void rc_tail_kernel(const double* __restrict__ Rc, int n, int64_t ldc,
-                                                     const double* __restrict__ Rs, int64_t lds_,
-                                                     double* __restrict__ X, int64_t ldx, double* __restrict__ R,
-                                                     int64_t ldr, const Ctrl* __restrict__ ctrl, int phase) {
+__device__ __forceinline__ void rc_tail_body(const double* __restrict__ Rc, int n, int64_t ldc,
+                                             const double* __restrict__ Rs, int64_t lds_,
+                                             double* __restrict__ X, int64_t ldx, double* __restrict__ R,
+                                             int64_t ldr, const Ctrl* __restrict__ ctrl, int phase, int b) {
   __shared__ __attribute__((aligned(16))) double lds[TRMM_LDS_DOUBLES];
   if (skip_launch(ctrl, P_AUTO, phase)) return;
-  const int b = blockIdx.x;
   if (b < n) {
     trinv_column(Rc, n, ldc, X, ldx, b);
     return;
@@ -63,10 +62,31 @@ __global__ __launch_bounds__(64) void rc_tail_kernel(const double* __restrict__ 
   trmm_tile(Rc, ldc, Rs, lds_, n, R, ldr, t % nbx, t / nbx, lds);
 }
 
+__global__ __launch_bounds__(64) void rc_tail_kernel(const double* __restrict__ Rc, int n, int64_t ldc,
+                                                     const double* __restrict__ Rs, int64_t lds_,
+                                                     double* __restrict__ X, int64_t ldx, double* __restrict__ R,
+                                                     int64_t ldr, const Ctrl* __restrict__ ctrl, int phase) {
+  rc_tail_body(Rc, n, ldc, Rs, lds_, X, ldx, R, ldr, ctrl, phase, blockIdx.x);
+}
+
+__host__ __device__ inline int rc_tail_blocks(int n) { return n + ((n + 15) / 16) * ((n + 63) / 64); }
+
+// Grouped: a member uses n + (its trmm tiles) workgroups.
+__global__ __launch_bounds__(64) void rc_tail_grouped(const BatchInst* __restrict__ bi,
+                                                      const int32_t* __restrict__ members, BatchCall call,
+                                                      int phase) {
+  const int i = bat_index(members);
+  const BatchInst& d = bi[i];
+  if ((int)blockIdx.x >= rc_tail_blocks(d.n)) return;
+  rc_tail_body(bat_ptr<const double>(call, d, d.off_Rc), d.n, d.n, bat_ptr<const double>(call, d, d.off_Rs), d.n,
+               bat_ptr<double>(call, d, d.off_Rci), d.n, call.R[i], call.ldr[i], bat_ptr<const Ctrl>(call, d, d.off_ctrl),
+               phase, blockIdx.x);
+}
+
 template <int NB, int NT>
-__global__ __launch_bounds__(NT == 2 ? 256 : 512) void qform_kernel(
+__device__ __forceinline__ void qform_body(
     const double* __restrict__ B, int m, int n, int64_t ldb, const double* __restrict__ X, int64_t ldx,
-    double* __restrict__ Q, int64_t ldq, const Ctrl* __restrict__ ctrl, int phase) {
+    double* __restrict__ Q, int64_t ldq, const Ctrl* __restrict__ ctrl, int phase, int bx, int gx) {
   constexpr int THREADS = NT == 2 ? 256 : 512;
   constexpr int WROWS = 16 * NT;                // rows per wave
   constexpr int ROWS = THREADS / 64 * WROWS;    // rows per workgroup pass
@@ -91,7 +111,7 @@ __global__ __launch_bounds__(NT == 2 ? 256 : 512) void qform_kernel(
   __syncthreads();
 
   const int64_t npass = ((int64_t)m + ROWS - 1) / ROWS;
-  int64_t pass = blockIdx.x;
+  int64_t pass = bx;
   if (pass >= npass) return;
 
   // K step of pair p, half h: q = p (h = 0) or NQ - 1 - p (h = 1)
@@ -229,7 +249,7 @@ __global__ __launch_bounds__(NT == 2 ? 256 : 512) void qform_kernel(
       if constexpr (c < NCH) load_fast(bufs[c], c, r0);
     });
     for (;;) {
-      const int64_t next = pass + gridDim.x;
+      const int64_t next = pass + gx;
       const bool more = next < nfull;
       const int64_t r0n = next * ROWS + WROWS * w;
       // X stays in LDS: its operand reads must not be hoisted out of the
@@ -258,7 +278,7 @@ __global__ __launch_bounds__(NT == 2 ? 256 : 512) void qform_kernel(
     }
   }
   // the ragged last pass, and every pass of other shapes
-  for (; pass < npass; pass += gridDim.x) {
+  for (; pass < npass; pass += gx) {
     const int64_t r0 = pass * ROWS + WROWS * w;
     Buf buf;
     asm volatile("" ::: "memory");
@@ -269,6 +289,56 @@ __global__ __launch_bounds__(NT == 2 ? 256 : 512) void qform_kernel(
     });
     store_any(r0);
   }
+}
+
+template <int NB, int NT>
+__global__ __launch_bounds__(NT == 2 ? 256 : 512) void qform_kernel(
+    const double* __restrict__ B, int m, int n, int64_t ldb, const double* __restrict__ X, int64_t ldx,
+    double* __restrict__ Q, int64_t ldq, const Ctrl* __restrict__ ctrl, int phase) {
+  qform_body<NB, NT>(B, m, n, ldb, X, ldx, Q, ldq, ctrl, phase, blockIdx.x, gridDim.x);
+}
+
+// Grouped: Q = B X of each member; a member uses its own block count.
+template <int NB, int NT>
+__global__ __launch_bounds__(NT == 2 ? 256 : 512) void qform_grouped(const BatchInst* __restrict__ bi,
+                                                                     const int32_t* __restrict__ members,
+                                                                     BatchCall call, int phase) {
+  const int i = bat_index(members);
+  const BatchInst& d = bi[i];
+  if ((int)blockIdx.x >= d.qform_blocks) return;
+  qform_body<NB, NT>(bat_ptr<const double>(call, d, d.off_B), d.m, d.n, d.m, bat_ptr<const double>(call, d, d.off_Rci),
+                     d.n, call.Q[i], call.ldq[i], bat_ptr<const Ctrl>(call, d, d.off_ctrl), phase, blockIdx.x,
+                     d.qform_blocks);
+}
+
+// Row passes per workgroup of Q = B X for an m-row member of a batch: about
+// four, at most one workgroup per compute unit.
+int qform_batch_blocks(int64_t m) {
+  constexpr int rows = (QF_NT == 2 ? 256 : 512) / 64 * 16 * QF_NT;
+  const int64_t npass = (m + rows - 1) / rows;
+  const int64_t b = (npass + 3) / 4;
+  return (int)(b < 1 ? 1 : (b > 256 ? 256 : b));
+}
+
+hipError_t launch_rc_tail_grouped(const BatchInst* bi, const int32_t* members, int count, int max_n,
+                                  const BatchCall& call, int phase, hipStream_t st) {
+  hipLaunchKernelGGL(rc_tail_grouped, dim3(rc_tail_blocks(max_n), count), dim3(64), 0, st, bi, members, call, phase);
+  return hipGetLastError();
+}
+
+// members share nb = ceil(n / 16)
+hipError_t launch_qform_grouped(int nb, const BatchInst* bi, const int32_t* members, int count, int max_blocks,
+                                const BatchCall& call, int phase, hipStream_t st) {
+  constexpr int NT = QF_NT;
+  const dim3 grid(max_blocks, count), block(NT == 2 ? 256 : 512);
+  switch (nb) {
+#define QF_CASE(K) \
+  case K: hipLaunchKernelGGL((qform_grouped<K, NT>), grid, block, 0, st, bi, members, call, phase); break;
+    QF_CASE(1) QF_CASE(2) QF_CASE(3) QF_CASE(4) QF_CASE(5) QF_CASE(6) QF_CASE(7) QF_CASE(8)
+#undef QF_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_trinv(const double* R, int n, int64_t ldr, double* X, int64_t ldx, const Ctrl* ctrl, int phase,

@@ -19,7 +19,7 @@
 // the 2^-11 / 2^-8 unit roundoff of the target format); FP32/FP64 rotate in
 // float64 along the lane's stride-4 row sequence and re-seed every 4 panels
 // (64 rotations, error ~1e-14).
-#include "common.hpp"
+#include "batch.hpp"
 
 namespace mrcqr {
 
@@ -103,11 +103,12 @@ __device__ __forceinline__ uint32_t group8_max_u32_dpp(uint32_t v) {
   return v;
 }
 
-template <int P>
-__global__ __launch_bounds__(SK_THREADS) void sketch_kernel(
+template <int P, bool FULL>
+__device__ __forceinline__ void sketch_body(
     const double* __restrict__ A, int64_t lda, int m, int n,
     const int32_t* __restrict__ S, int s, uint64_t seed, int rows_per_chunk,
-    typename SkT<P>::acc* __restrict__ Ypart, const Ctrl* __restrict__ ctrl, int phase) {
+    typename SkT<P>::acc* __restrict__ Ypart, const Ctrl* __restrict__ ctrl, int phase,
+    int chunk, int cblk, int sblk) {
   using T = SkT<P>;
   using elem = typename T::elem;
   using acc_t = typename T::acc;
@@ -124,9 +125,18 @@ __global__ __launch_bounds__(SK_THREADS) void sketch_kernel(
 
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63, g = l >> 4, c16 = l & 15;
-  const int chunk = blockIdx.x;
-  const int cbase = blockIdx.y * SK_NBLK;
-  const int sbase = blockIdx.z * SK_SBLK + w * 32;
+  const int cbase = cblk * SK_NBLK;
+  const int sbase = sblk * SK_SBLK + w * 32;
+  // FULL: the block's 128 columns and 256 sketch rows all exist. Otherwise
+  // column tiles at or past n and M tiles of rows at or past s are skipped
+  // (their products were zero and never stored; every stored sum goes
+  // through the same products in the same order either way).
+  const int ncol = FULL ? SK_NBLK : min(n - cbase, SK_NBLK);
+  const int ntile = FULL ? 8 : (ncol + 15) >> 4;
+  const bool wload = FULL || w * 16 < ncol;  // this wave loads columns that exist
+  bool mt_on[2];
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt) mt_on[mt] = FULL || sbase + 16 * mt < s;
   const int64_t tstart = (int64_t)chunk * rows_per_chunk;
   const int64_t tend = min((int64_t)m, tstart + rows_per_chunk);
   const int npanels = (int)((tend - tstart + SK_PANEL - 1) / SK_PANEL);
@@ -178,6 +188,7 @@ __global__ __launch_bounds__(SK_THREADS) void sketch_kernel(
   double regs[16];
   const int lrow = 8 * (l & 7);
   auto load_panel = [&](int64_t t0) {
+    if (!wload) return;
     if (t0 + SK_PANEL <= tend && cbase + SK_NBLK <= n) {
 #pragma unroll
       for (int r = 0; r < 2; ++r) {
@@ -220,6 +231,7 @@ __global__ __launch_bounds__(SK_THREADS) void sketch_kernel(
     const uint32_t smask = (uint32_t)(sgnm[buf] >> lrow) & 0xFFu;
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
+      if (!wload) continue;
       const int cl = w * 16 + r * 8 + (l >> 3);
       int e = 0;
       if constexpr (LOWP) {
@@ -279,9 +291,10 @@ __global__ __launch_bounds__(SK_THREADS) void sketch_kernel(
         vec8 bop[8];
 #pragma unroll
         for (int nt = 0; nt < 8; ++nt)
-          bop[nt] = *reinterpret_cast<const vec8*>(&tb[(16 * nt + c16) * LD + KSTEP * ks + 8 * g]);
+          if (nt < ntile) bop[nt] = *reinterpret_cast<const vec8*>(&tb[(16 * nt + c16) * LD + KSTEP * ks + 8 * g]);
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt) {
+          if (!mt_on[mt]) continue;
           // run of 8 consecutive rows starting 32*ks rows after the base:
           // first two values by rotation, the rest by the three-term
           // recurrence cos((t+1)w) = 2 cos(w) cos(tw) - cos((t-1)w). Rows
@@ -301,6 +314,7 @@ __global__ __launch_bounds__(SK_THREADS) void sketch_kernel(
           }
 #pragma unroll
           for (int nt = 0; nt < 8; ++nt) {
+            if (nt >= ntile) continue;
             const accv cin = (ks == 0) ? accv{0, 0, 0, 0} : accp[mt][nt];
             if constexpr (P == P_FP16) accp[mt][nt] = mfma_f16(aop, bop[nt], cin);
             else accp[mt][nt] = mfma_bf16(aop, bop[nt], cin);
@@ -320,12 +334,14 @@ __global__ __launch_bounds__(SK_THREADS) void sketch_kernel(
       for (int ks = 0; ks < NKS; ++ks) {
         elem bop[8];
 #pragma unroll
-        for (int nt = 0; nt < 8; ++nt) bop[nt] = tb[(16 * nt + c16) * LD + KSTEP * ks + g];
+        for (int nt = 0; nt < 8; ++nt)
+          if (nt < ntile) bop[nt] = tb[(16 * nt + c16) * LD + KSTEP * ks + g];
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt) {
           const elem a = kvalid[mt] ? (elem)cb[mt] : (elem)0.0;
 #pragma unroll
           for (int nt = 0; nt < 8; ++nt) {
+            if (!mt_on[mt] || nt >= ntile) continue;
             if constexpr (P == P_FP32) accp[mt][nt] = mfma_f32(a, bop[nt], accp[mt][nt]);
             else acc[mt][nt] = mfma_f64(a, bop[nt], acc[mt][nt]);
           }
@@ -341,9 +357,11 @@ __global__ __launch_bounds__(SK_THREADS) void sketch_kernel(
       // undo the block prescale of this panel (one power of two per column)
 #pragma unroll
       for (int nt = 0; nt < 8; ++nt) {
+        if (nt >= ntile) continue;
         const float sc = esc[buf][16 * nt + c16];
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt) {
+          if (!mt_on[mt]) continue;
 #pragma unroll
           for (int r = 0; r < 4; ++r) acc[mt][nt][r] = fmaf(accp[mt][nt][r], sc, acc[mt][nt][r]);
           if constexpr (KSTEP != 32) accp[mt][nt] = accv{0, 0, 0, 0};
@@ -367,12 +385,36 @@ __global__ __launch_bounds__(SK_THREADS) void sketch_kernel(
     }
 }
 
+template <int P, bool FULL>
+__global__ __launch_bounds__(SK_THREADS) void sketch_kernel(
+    const double* __restrict__ A, int64_t lda, int m, int n,
+    const int32_t* __restrict__ S, int s, uint64_t seed, int rows_per_chunk,
+    typename SkT<P>::acc* __restrict__ Ypart, const Ctrl* __restrict__ ctrl, int phase) {
+  sketch_body<P, FULL>(A, lda, m, n, S, s, seed, rows_per_chunk, Ypart, ctrl, phase, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// Grouped (members with n <= 128 and s <= 256: one column block and one
+// sketch-row block each); blockIdx.x is the row chunk. Members are grouped
+// by the variant a single call of their shape uses (FULL when n = 128 and
+// s = 256), since the two may round the coefficients differently.
+template <int P, bool FULL>
+__global__ __launch_bounds__(SK_THREADS) void sketch_grouped(const BatchInst* __restrict__ bi,
+                                                             const int32_t* __restrict__ members, BatchCall call,
+                                                             int phase) {
+  const int i = bat_index(members);
+  const BatchInst& d = bi[i];
+  if ((int)blockIdx.x >= d.sk_chunks) return;
+  sketch_body<P, FULL>(call.A[i], call.lda[i], d.m, d.n, bat_ptr<int32_t>(call, d, d.off_S), d.s, call.seed[i],
+                       d.sk_rows, bat_ptr<typename SkT<P>::acc>(call, d, d.off_Ypart),
+                       bat_ptr<Ctrl>(call, d, d.off_ctrl), phase, blockIdx.x, 0, 0);
+}
+
 // Y[srow, col] = gamma_k * sum over chunks (float64, fixed order), then
 // rounded to float32 for the low-precision sketches. A block covers 64
 // consecutive (col, srow) entries; its 4 waves sum 4 contiguous chunk
 // ranges, combined in LDS in fixed order.
 template <typename AccT>
-__global__ __launch_bounds__(256) void sketch_reduce_kernel(const AccT* __restrict__ Ypart, int chunks, int n, int s,
+__device__ __forceinline__ void sketch_reduce_body(const AccT* __restrict__ Ypart, int chunks, int n, int s,
                                      const int32_t* __restrict__ S, double* __restrict__ Y, int64_t ldy,
                                      int round_f32, const Ctrl* __restrict__ ctrl, int slot, int phase) {
   if (skip_launch(ctrl, slot, phase)) return;
@@ -407,8 +449,31 @@ __global__ __launch_bounds__(256) void sketch_reduce_kernel(const AccT* __restri
   }
 }
 
+template <typename AccT>
+__global__ __launch_bounds__(256) void sketch_reduce_kernel(const AccT* __restrict__ Ypart, int chunks, int n, int s,
+                                     const int32_t* __restrict__ S, double* __restrict__ Y, int64_t ldy,
+                                     int round_f32, const Ctrl* __restrict__ ctrl, int slot, int phase) {
+  sketch_reduce_body<AccT>(Ypart, chunks, n, s, S, Y, ldy, round_f32, ctrl, slot, phase);
+}
+
+template <typename AccT>
+__global__ __launch_bounds__(256) void sketch_reduce_grouped(const BatchInst* __restrict__ bi,
+                                                             const int32_t* __restrict__ members, BatchCall call,
+                                                             int round_f32, int slot, int phase) {
+  const int i = bat_index(members);
+  const BatchInst& d = bi[i];
+  if ((int64_t)blockIdx.x * 64 >= (int64_t)d.n * d.s) return;
+  sketch_reduce_body<AccT>(bat_ptr<const AccT>(call, d, d.off_Ypart), d.sk_chunks, d.n, d.s,
+                           bat_ptr<const int32_t>(call, d, d.off_S), bat_ptr<double>(call, d, d.off_Y), d.s, round_f32,
+                           bat_ptr<const Ctrl>(call, d, d.off_ctrl), slot, phase);
+}
+
 // ---- host-side launch -------------------------------------------------
 struct SketchGeom { int chunks, rows_per_chunk; };
+
+// every block of an (n, s) sketch covers 128 existing columns and 256
+// existing sketch rows
+bool sketch_full_tiles(int n, int s) { return n % SK_NBLK == 0 && s % SK_SBLK == 0; }
 
 SketchGeom sketch_geometry(int64_t m) {
   const int64_t npan = (m + SK_PANEL - 1) / SK_PANEL;
@@ -434,23 +499,60 @@ hipError_t launch_sketch(int prec, const double* A, int64_t lda, int m, int n, c
   dim3 block(SK_THREADS);
   const int rb = 256;
   const int64_t tot = (int64_t)n * s;
+  const bool full = sketch_full_tiles(n, s);  // every block's tile exists whole
   dim3 rgrid((unsigned)((tot + 63) / 64));
   switch (prec) {
     case P_FP16:
-      hipLaunchKernelGGL(sketch_kernel<P_FP16>, grid, block, 0, st, A, lda, m, n, S, s, seed, gg.rows_per_chunk, (float*)Ypart, ctrl, phase);
+      if (full) hipLaunchKernelGGL((sketch_kernel<P_FP16, true>), grid, block, 0, st, A, lda, m, n, S, s, seed, gg.rows_per_chunk, (float*)Ypart, ctrl, phase);
+      else hipLaunchKernelGGL((sketch_kernel<P_FP16, false>), grid, block, 0, st, A, lda, m, n, S, s, seed, gg.rows_per_chunk, (float*)Ypart, ctrl, phase);
       hipLaunchKernelGGL(sketch_reduce_kernel<float>, rgrid, dim3(rb), 0, st, (const float*)Ypart, gg.chunks, n, s, S, Y, ldy, 1, ctrl, (int)P_FP16, phase);
       break;
     case P_BF16:
-      hipLaunchKernelGGL(sketch_kernel<P_BF16>, grid, block, 0, st, A, lda, m, n, S, s, seed, gg.rows_per_chunk, (float*)Ypart, ctrl, phase);
+      if (full) hipLaunchKernelGGL((sketch_kernel<P_BF16, true>), grid, block, 0, st, A, lda, m, n, S, s, seed, gg.rows_per_chunk, (float*)Ypart, ctrl, phase);
+      else hipLaunchKernelGGL((sketch_kernel<P_BF16, false>), grid, block, 0, st, A, lda, m, n, S, s, seed, gg.rows_per_chunk, (float*)Ypart, ctrl, phase);
       hipLaunchKernelGGL(sketch_reduce_kernel<float>, rgrid, dim3(rb), 0, st, (const float*)Ypart, gg.chunks, n, s, S, Y, ldy, 1, ctrl, (int)P_BF16, phase);
       break;
     case P_FP32:
-      hipLaunchKernelGGL(sketch_kernel<P_FP32>, grid, block, 0, st, A, lda, m, n, S, s, seed, gg.rows_per_chunk, (float*)Ypart, ctrl, phase);
+      if (full) hipLaunchKernelGGL((sketch_kernel<P_FP32, true>), grid, block, 0, st, A, lda, m, n, S, s, seed, gg.rows_per_chunk, (float*)Ypart, ctrl, phase);
+      else hipLaunchKernelGGL((sketch_kernel<P_FP32, false>), grid, block, 0, st, A, lda, m, n, S, s, seed, gg.rows_per_chunk, (float*)Ypart, ctrl, phase);
       hipLaunchKernelGGL(sketch_reduce_kernel<float>, rgrid, dim3(rb), 0, st, (const float*)Ypart, gg.chunks, n, s, S, Y, ldy, 1, ctrl, (int)P_FP32, phase);
       break;
     case P_FP64:
-      hipLaunchKernelGGL(sketch_kernel<P_FP64>, grid, block, 0, st, A, lda, m, n, S, s, seed, gg.rows_per_chunk, (double*)Ypart, ctrl, phase);
+      if (full) hipLaunchKernelGGL((sketch_kernel<P_FP64, true>), grid, block, 0, st, A, lda, m, n, S, s, seed, gg.rows_per_chunk, (double*)Ypart, ctrl, phase);
+      else hipLaunchKernelGGL((sketch_kernel<P_FP64, false>), grid, block, 0, st, A, lda, m, n, S, s, seed, gg.rows_per_chunk, (double*)Ypart, ctrl, phase);
       hipLaunchKernelGGL(sketch_reduce_kernel<double>, rgrid, dim3(rb), 0, st, (const double*)Ypart, gg.chunks, n, s, S, Y, ldy, 0, ctrl, (int)P_FP64, phase);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// Stage 1's sketch for every member of a batch at precision prec: grid
+// (largest chunk count, members), then the reduction.
+hipError_t launch_sketch_grouped(int prec, bool full, const BatchInst* bi, const int32_t* members, int count,
+                                 int max_chunks, int64_t max_ns, const BatchCall& call, int phase, hipStream_t st) {
+  const dim3 grid(max_chunks, count), rgrid((unsigned)((max_ns + 63) / 64), count);
+  switch (prec) {
+    case P_FP16:
+      if (full) hipLaunchKernelGGL((sketch_grouped<P_FP16, true>), grid, dim3(SK_THREADS), 0, st, bi, members, call, phase);
+      else hipLaunchKernelGGL((sketch_grouped<P_FP16, false>), grid, dim3(SK_THREADS), 0, st, bi, members, call, phase);
+      hipLaunchKernelGGL(sketch_reduce_grouped<float>, rgrid, dim3(256), 0, st, bi, members, call, 1, (int)P_FP16, phase);
+      break;
+    case P_BF16:
+      if (full) hipLaunchKernelGGL((sketch_grouped<P_BF16, true>), grid, dim3(SK_THREADS), 0, st, bi, members, call, phase);
+      else hipLaunchKernelGGL((sketch_grouped<P_BF16, false>), grid, dim3(SK_THREADS), 0, st, bi, members, call, phase);
+      hipLaunchKernelGGL(sketch_reduce_grouped<float>, rgrid, dim3(256), 0, st, bi, members, call, 1, (int)P_BF16, phase);
+      break;
+    case P_FP32:
+      if (full) hipLaunchKernelGGL((sketch_grouped<P_FP32, true>), grid, dim3(SK_THREADS), 0, st, bi, members, call, phase);
+      else hipLaunchKernelGGL((sketch_grouped<P_FP32, false>), grid, dim3(SK_THREADS), 0, st, bi, members, call, phase);
+      hipLaunchKernelGGL(sketch_reduce_grouped<float>, rgrid, dim3(256), 0, st, bi, members, call, 1, (int)P_FP32, phase);
+      break;
+    case P_FP64:
+      if (full) hipLaunchKernelGGL((sketch_grouped<P_FP64, true>), grid, dim3(SK_THREADS), 0, st, bi, members, call, phase);
+      else hipLaunchKernelGGL((sketch_grouped<P_FP64, false>), grid, dim3(SK_THREADS), 0, st, bi, members, call, phase);
+      hipLaunchKernelGGL(sketch_reduce_grouped<double>, rgrid, dim3(256), 0, st, bi, members, call, 0, (int)P_FP64, phase);
       break;
     default:
       return hipErrorInvalidValue;

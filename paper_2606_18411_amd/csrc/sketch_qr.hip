@@ -14,7 +14,7 @@
 // rows and is widened to float64.
 //
 // The ICE estimate (Bischof 1990) of kappa_2 runs in wave 0 afterwards.
-#include "common.hpp"
+#include "batch.hpp"
 #include "ice.hpp"
 
 namespace mrcqr {
@@ -186,7 +186,7 @@ __global__ __launch_bounds__(NT) void householder_kernel(
 // updated first by its group, which then forms the next reflector while
 // the other columns are still being updated (one barrier per step).
 template <typename T, int NT, int CPT, int RPT>
-__global__ __launch_bounds__(NT) void householder16_kernel(
+__device__ __forceinline__ void householder16_body(
     const double* __restrict__ Y, int s, int n, int64_t ldy,
     double* __restrict__ Rs, int64_t ldr, double* __restrict__ kappa_out,
     Ctrl* __restrict__ ctrl, int slot, int phase, int want_kappa) {
@@ -348,6 +348,26 @@ __global__ __launch_bounds__(NT) void householder16_kernel(
 }
 
 // Stand-alone ICE of an upper-triangular matrix (two waves).
+template <typename T, int NT, int CPT, int RPT>
+__global__ __launch_bounds__(NT) void householder16_kernel(
+    const double* __restrict__ Y, int s, int n, int64_t ldy,
+    double* __restrict__ Rs, int64_t ldr, double* __restrict__ kappa_out,
+    Ctrl* __restrict__ ctrl, int slot, int phase, int want_kappa) {
+  householder16_body<T, NT, CPT, RPT>(Y, s, n, ldy, Rs, ldr, kappa_out, ctrl, slot, phase, want_kappa);
+}
+
+// Grouped: one workgroup per member (all members share the configuration).
+template <typename T, int NT, int CPT, int RPT>
+__global__ __launch_bounds__(NT) void householder16_grouped(const BatchInst* __restrict__ bi,
+                                                            const int32_t* __restrict__ members, BatchCall call,
+                                                            int slot, int phase) {
+  const int i = bat_index(members);
+  const BatchInst& d = bi[i];
+  householder16_body<T, NT, CPT, RPT>(bat_ptr<const double>(call, d, d.off_Y), d.s, d.n, d.s,
+                                      bat_ptr<double>(call, d, d.off_Rs), d.n, nullptr,
+                                      bat_ptr<Ctrl>(call, d, d.off_ctrl), slot, phase, 0);
+}
+
 __global__ void condest_kernel(const double* __restrict__ R, int n, int64_t ldr, double* __restrict__ kappa_out) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   double* Rl = reinterpret_cast<double*>(smem);
@@ -418,6 +438,16 @@ static bool qr16_config(int s, int n, int& nt, int& cpt, int& rpt) {
   return false;
 }
 
+template <typename T, int NT, int CPT, int RPT>
+static hipError_t launch_qr16_grouped(const BatchInst* bi, const int32_t* members, int count, int max_n,
+                                      const BatchCall& call, int slot, int phase, hipStream_t st) {
+  const size_t sm = 2 * (size_t)16 * RPT * sizeof(T) + (size_t)max_n * max_n * 8 + 2 * sizeof(T) + (size_t)max_n * 4 + 64;
+  allow_dynamic_lds(reinterpret_cast<const void*>(&householder16_grouped<T, NT, CPT, RPT>), sm);
+  hipLaunchKernelGGL((householder16_grouped<T, NT, CPT, RPT>), dim3(1, count), dim3(NT), sm, st, bi, members, call,
+                     slot, phase);
+  return hipGetLastError();
+}
+
 template <typename T>
 static hipError_t launch_qr_t(const double* Y, int s, int n, int64_t ldy, double* Rs, int64_t ldr,
                               double* kappa, Ctrl* ctrl, int slot, int phase, hipStream_t st) {
@@ -456,6 +486,33 @@ hipError_t launch_sketch_qr(bool f64, const double* Y, int s, int n, int64_t ldy
                             double* kappa, Ctrl* ctrl, int slot, int phase, hipStream_t st) {
   return f64 ? launch_qr_t<double>(Y, s, n, ldy, Rs, ldr, kappa, ctrl, slot, phase, st)
              : launch_qr_t<float>(Y, s, n, ldy, Rs, ldr, kappa, ctrl, slot, phase, st);
+}
+
+// Configuration key of the sketch QR of an (s, n) sketch for a grouped
+// launch: nt * 10000 + cpt * 100 + rpt, or -1 when the shape needs the
+// general kernel (never for s <= 256).
+int qr_group_key(bool f64, int s, int n) {
+  int nt, cpt, rpt;
+  const bool ok = f64 ? qr16_config<double>(s, n, nt, cpt, rpt) : qr16_config<float>(s, n, nt, cpt, rpt);
+  return ok ? nt * 10000 + cpt * 100 + rpt : -1;
+}
+
+hipError_t launch_sketch_qr_grouped(bool f64, int key, const BatchInst* bi, const int32_t* members, int count,
+                                    int max_n, const BatchCall& call, int slot, int phase, hipStream_t st) {
+  const int nt = key / 10000, cpt = (key / 100) % 100, rpt = key % 100;
+#define QRG(T, N, C, R)                                     \
+  if (nt == N && cpt == C && rpt == R)                      \
+    return launch_qr16_grouped<T, N, C, R>(bi, members, count, max_n, call, slot, phase, st)
+  if (!f64) {
+    QRG(float, 1024, 1, 4); QRG(float, 1024, 1, 8); QRG(float, 1024, 1, 16); QRG(float, 1024, 1, 32);
+    QRG(float, 1024, 2, 4); QRG(float, 1024, 2, 8); QRG(float, 1024, 2, 16);
+  } else {
+    QRG(double, 1024, 1, 4); QRG(double, 1024, 1, 8); QRG(double, 1024, 1, 16);
+    QRG(double, 1024, 2, 4); QRG(double, 1024, 2, 8);
+    QRG(double, 512, 4, 16); QRG(double, 512, 2, 32);
+  }
+#undef QRG
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_condest(const double* R, int n, int64_t ldr, double* kappa, hipStream_t st) {

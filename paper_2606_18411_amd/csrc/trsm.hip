@@ -18,7 +18,7 @@
 // tile to one row per lane, the 64 lanes run the forward substitution with
 // wave-uniform diagonal-block rows (scalar loads), and the solved columns
 // return to B-operand registers and to X.
-#include "common.hpp"
+#include "batch.hpp"
 
 namespace mrcqr {
 
@@ -36,12 +36,13 @@ size_t trsm_workspace_bytes(int n) {
   return ((size_t)tr_rop_size(nb) + (size_t)nb * 256) * sizeof(double) + 256;
 }
 
-__global__ void trsm_prep_kernel(const double* __restrict__ R, int n, int64_t ldr, double* __restrict__ Rop,
-                                 double* __restrict__ Dg, const Ctrl* __restrict__ ctrl, int phase) {
+__device__ __forceinline__ void trsm_prep_body(const double* __restrict__ R, int n, int64_t ldr,
+                                               double* __restrict__ Rop, double* __restrict__ Dg,
+                                               const Ctrl* __restrict__ ctrl, int phase, int bx, int gx) {
   if (skip_launch(ctrl, P_AUTO, phase)) return;
   const int nb = (n + 15) / 16;
   const int nrop = tr_rop_size(nb);
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nrop + nb * 256; e += gridDim.x * blockDim.x) {
+  for (int e = bx * blockDim.x + threadIdx.x; e < nrop + nb * 256; e += gx * blockDim.x) {
     if (e < nrop) {
       // invert off(J, q) + lane
       int J = 1;
@@ -64,6 +65,22 @@ __global__ void trsm_prep_kernel(const double* __restrict__ R, int n, int64_t ld
   }
 }
 
+__global__ void trsm_prep_kernel(const double* __restrict__ R, int n, int64_t ldr, double* __restrict__ Rop,
+                                 double* __restrict__ Dg, const Ctrl* __restrict__ ctrl, int phase) {
+  trsm_prep_body(R, n, ldr, Rop, Dg, ctrl, phase, blockIdx.x, gridDim.x);
+}
+
+// Grouped: Rs of each member into its operand arrays (grid-stride over the
+// largest member's element count).
+__global__ void trsm_prep_grouped(const BatchInst* __restrict__ bi, const int32_t* __restrict__ members,
+                                  BatchCall call, int phase) {
+  const int i = bat_index(members);
+  const BatchInst& d = bi[i];
+  double* Rop = bat_ptr<double>(call, d, d.off_Tw);
+  trsm_prep_body(bat_ptr<const double>(call, d, d.off_Rs), d.n, d.n, Rop, Rop + tr_rop_size((d.n + 15) / 16),
+                 bat_ptr<const Ctrl>(call, d, d.off_ctrl), phase, blockIdx.x, gridDim.x);
+}
+
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -71,10 +88,10 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 template <int NMAX>
-__global__ __launch_bounds__(TR_THREADS) void trsm_kernel(
+__device__ __forceinline__ void trsm_body(
     const double* __restrict__ A, int m, int n, int64_t lda,
     const double* __restrict__ Rop, const double* __restrict__ Dg,
-    double* __restrict__ X, int64_t ldx, const Ctrl* __restrict__ ctrl, int phase) {
+    double* __restrict__ X, int64_t ldx, const Ctrl* __restrict__ ctrl, int phase, int bx, int gx) {
   constexpr int NB = NMAX / 16;
   constexpr int RSZ = tr_rop_size(NB);
   __shared__ __attribute__((aligned(16))) double Rl[RSZ];
@@ -89,7 +106,7 @@ __global__ __launch_bounds__(TR_THREADS) void trsm_kernel(
   __syncthreads();
 
   double* Tw = Tt[w];
-  for (int64_t pan = blockIdx.x; pan * TR_ROWS < m; pan += gridDim.x) {
+  for (int64_t pan = bx; pan * TR_ROWS < m; pan += gx) {
     const int64_t r0 = pan * TR_ROWS + TR_WROWS * w;
     double xb[4 * NB][4];
     double an[4][4];
@@ -150,6 +167,53 @@ __global__ __launch_bounds__(TR_THREADS) void trsm_kernel(
       wave_lds_sync();
     }
   }
+}
+
+template <int NMAX>
+__global__ __launch_bounds__(TR_THREADS) void trsm_kernel(
+    const double* __restrict__ A, int m, int n, int64_t lda,
+    const double* __restrict__ Rop, const double* __restrict__ Dg,
+    double* __restrict__ X, int64_t ldx, const Ctrl* __restrict__ ctrl, int phase) {
+  trsm_body<NMAX>(A, m, n, lda, Rop, Dg, X, ldx, ctrl, phase, blockIdx.x, gridDim.x);
+}
+
+// Grouped: B = A Rs^{-1} of each member; a member uses its own block count.
+template <int NMAX>
+__global__ __launch_bounds__(TR_THREADS) void trsm_grouped(const BatchInst* __restrict__ bi,
+                                                           const int32_t* __restrict__ members, BatchCall call,
+                                                           int phase) {
+  const int i = bat_index(members);
+  const BatchInst& d = bi[i];
+  if ((int)blockIdx.x >= d.trsm_blocks) return;
+  const double* Rop = bat_ptr<const double>(call, d, d.off_Tw);
+  trsm_body<NMAX>(call.A[i], d.m, d.n, call.lda[i], Rop, Rop + tr_rop_size((d.n + 15) / 16),
+                  bat_ptr<double>(call, d, d.off_B), d.m, bat_ptr<const Ctrl>(call, d, d.off_ctrl), phase, blockIdx.x,
+                  d.trsm_blocks);
+}
+
+// Blocks of the solve for an m-row member of a batch: about four row panels
+// per workgroup, at most one workgroup per compute unit.
+int trsm_batch_blocks(int64_t m) {
+  const int64_t panels = (m + TR_ROWS - 1) / TR_ROWS;
+  const int64_t b = (panels + 3) / 4;
+  return (int)(b < 1 ? 1 : (b > 256 ? 256 : b));
+}
+
+hipError_t launch_trsm_grouped(int nmax, const BatchInst* bi, const int32_t* members, int count, int max_elems,
+                               int max_blocks, const BatchCall& call, int phase, hipStream_t st) {
+  hipLaunchKernelGGL(trsm_prep_grouped, dim3((max_elems + 255) / 256, count), dim3(256), 0, st, bi, members, call,
+                     phase);
+  const dim3 grid(max_blocks, count);
+  if (nmax == 32) hipLaunchKernelGGL(trsm_grouped<32>, grid, dim3(TR_THREADS), 0, st, bi, members, call, phase);
+  else if (nmax == 64) hipLaunchKernelGGL(trsm_grouped<64>, grid, dim3(TR_THREADS), 0, st, bi, members, call, phase);
+  else if (nmax == 128) hipLaunchKernelGGL(trsm_grouped<128>, grid, dim3(TR_THREADS), 0, st, bi, members, call, phase);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+int trsm_prep_elems(int n) {
+  const int nb = (n + 15) / 16;
+  return tr_rop_size(nb) + nb * 256;
 }
 
 hipError_t launch_trsm(const double* A, int m, int n, int64_t lda, const double* R, int64_t ldr,

@@ -1,0 +1,152 @@
+"""Batches of uneven factorizations as grouped launches (one launch per step
+and kernel configuration): every member's Q, R and info must be bitwise those
+of a single call with the same input, policy and seed; invalid per-member
+arguments are caught on the device; the batch replays from a captured graph;
+and the uneven mix of 512 members (m in [4096, 131072], n in {8, 16, 32, 64},
+kappa log-uniform in [1e2, 1e12], AUTO) runs to completion."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import metrics as MT
+from gpu_common import require_gpu, to_dev, to_host, progress, torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def M():
+    return require_gpu()
+
+
+# ragged shapes across every size class of n, mixed policies
+MIX = [(100, 1, 10.0, "fp64"), (129, 7, 1e2, "fp16"), (4103, 8, 1e3, "auto"), (5000, 16, 1e6, "auto"),
+       (7001, 31, 1e10, "auto"), (9000, 32, 1e2, "bf16"), (3000, 33, 1e4, "fp32"), (20000, 48, 1e5, "auto_carry"),
+       (128, 64, 1e2, "fp64"), (33333, 64, 1e7, "auto"), (12345, 100, 1e3, "fp16"), (70001, 128, 1e4, "auto"),
+       (50000, 96, 1e12, "auto"), (4096, 128, 1e8, "fp32"), (1000, 5, 1e14, "auto"), (8192, 64, 1e9, "fp16")]
+
+
+def _single(M, A, prec, seed):
+    m, n = A.shape
+    plan = M.Plan(m, n)  # fresh zeroed workspace, like the batch's
+    Q, R = M.empty_colmajor(m, n), M.empty_colmajor(n, n)
+    plan.execute(A, Q, R, prec, seed=seed)
+    torch.cuda.synchronize()
+    return Q, R, plan.last_info()
+
+
+def _outputs(M, shapes):
+    return [M.empty_colmajor(m, n) for m, n in shapes], [M.empty_colmajor(n, n) for _, n in shapes]
+
+
+def test_batch_bitwise_equals_single_calls(M):
+    progress("batch vs single, mixed shapes and policies")
+    As = [to_dev(W.test_matrix(m, n, k, 3000 + i)) for i, (m, n, k, _) in enumerate(MIX)]
+    precs = [p for *_, p in MIX]
+    seeds = [17 * i + 1 for i in range(len(MIX))]
+    shapes = [(m, n) for m, n, *_ in MIX]
+    bp = M.BatchPlan(shapes)
+    Qs, Rs = _outputs(M, shapes)
+    bp.bind(As, Qs, Rs, precs, seeds)
+    bp.execute()
+    torch.cuda.synchronize()
+    infos = bp.last_infos()
+    for i, (A, p, sd) in enumerate(zip(As, precs, seeds)):
+        Q1, R1, inf1 = _single(M, A, p, sd)
+        assert _same_info(infos[i], inf1), (i, infos[i], inf1)
+        if inf1.status in (0, 7):
+            assert torch.equal(Qs[i], Q1) and torch.equal(Rs[i], R1), i
+    assert sum(inf.status == 0 for inf in infos) >= len(MIX) - 2, infos
+
+
+def _same_info(a, b):
+    same_float = lambda x, y: (np.isnan(x) and np.isnan(y)) or x == y
+    return ((a.status, a.precision_used, a.chol_fail_index, a.escalations) ==
+            (b.status, b.precision_used, b.chol_fail_index, b.escalations) and
+            same_float(a.kappa_rs_est, b.kappa_rs_est) and same_float(a.kappa_rc_est, b.kappa_rc_est))
+
+
+def test_batch_invalid_member_is_skipped(M):
+    progress("batch with an invalid member")
+    shapes = [(2000, 16), (3000, 32), (2500, 8)]
+    As = [to_dev(W.test_matrix(m, n, 1e3, 3100 + i)) for i, (m, n) in enumerate(shapes)]
+    bp = M.BatchPlan(shapes)
+    Qs, Rs = _outputs(M, shapes)
+    bp.bind(As, Qs, Rs, "fp16", [1, 2, 3])
+    bp._args[5][1] = shapes[1][0] - 1  # ldq < m for member 1
+    Q1_before = Qs[1].clone()
+    bp.execute()
+    torch.cuda.synchronize()
+    infos = bp.last_infos()
+    assert infos[1].status == 1, infos[1]
+    assert torch.equal(Qs[1], Q1_before)  # untouched
+    for i in (0, 2):
+        Qr, Rr, inf = _single(M, As[i], "fp16", i + 1)
+        assert infos[i].status == 0 and torch.equal(Qs[i], Qr) and torch.equal(Rs[i], Rr)
+
+
+def test_batch_graph_replays(M):
+    progress("batch graph capture")
+    shapes = [(6000, 16), (9000, 64), (4096, 32), (11111, 128)]
+    first = [to_dev(W.test_matrix(m, n, 1e2, 3200 + i)) for i, (m, n) in enumerate(shapes)]
+    second = [to_dev(W.test_matrix(m, n, 1e9, 3300 + i)) for i, (m, n) in enumerate(shapes)]
+    As = [M.empty_colmajor(m, n) for m, n in shapes]
+    Qs, Rs = _outputs(M, shapes)
+    bp = M.BatchPlan(shapes)
+    bp.bind(As, Qs, Rs, "auto", [5, 6, 7, 8])
+    for a, b in zip(As, first):
+        a.copy_(b)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        bp.execute()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        bp.execute()
+    torch.cuda.synchronize()
+    for rep, src in enumerate([second, first, second]):
+        for a, b in zip(As, src):
+            a.copy_(b)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        infos = bp.last_infos()
+        for i, a in enumerate(src):
+            Qr, Rr, inf = _single(M, a, "auto", 5 + i)
+            assert (infos[i].status, infos[i].precision_used) == (inf.status, inf.precision_used), (rep, i)
+            assert torch.equal(Qs[i], Qr) and torch.equal(Rs[i], Rr), (rep, i)
+
+
+def test_uneven_mix_512(M):
+    mix = W.instance_mix(512, 2024)
+    progress("uneven mix of 512: drawing inputs on the device")
+    As = [W.device_test_matrix(m, n, k, 4000 + i) for i, (m, n, k) in enumerate(mix)]
+    shapes = [(m, n) for m, n, _ in mix]
+    seeds = list(range(1, 513))
+    bp = M.BatchPlan(shapes)
+    Qs, Rs = _outputs(M, shapes)
+    bp.bind(As, Qs, Rs, "auto", seeds)
+    bp.execute()  # warm-up
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    times = []
+    for _ in range(3):
+        ev0.record()
+        bp.execute()
+        ev1.record()
+        torch.cuda.synchronize()
+        times.append(ev0.elapsed_time(ev1))
+    infos = bp.last_infos()
+    assert all(inf.status == 0 for inf in infos), [(i, inf) for i, inf in enumerate(infos) if inf.status != 0][:4]
+    pr = [inf.precision for inf in infos]
+    gbytes = sum(m * n * 8 for m, n in shapes) / 1e9
+    progress(f"uneven mix of 512 ({gbytes:.2f} GB of A): {min(times):.2f} ms per batch (best of 3); "
+             f"fp16/fp32/fp64 = {pr.count('fp16')}/{pr.count('fp32')}/{pr.count('fp64')}")
+    for i in np.random.default_rng(0).choice(512, 6, replace=False):
+        Qh, Rh = to_host(Qs[i]), to_host(Rs[i])
+        assert MT.orthogonality(Qh) <= 1e-13, i
+        assert MT.residual(to_host(As[i]), Qh, Rh, 1.0) <= 1e-13, i
+        Qr, Rr, inf = _single(M, As[i], "auto", seeds[i])
+        assert torch.equal(Qs[i], Qr) and torch.equal(Rs[i], Rr), i

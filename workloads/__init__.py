@@ -20,6 +20,7 @@ from .matrices import (
     spd_matrix,
     instance_mix,
     rising_kappas,
+    device_test_matrix,
 )
 
 __all__ = [
@@ -31,4 +32,5 @@ __all__ = [
     "spd_matrix",
     "instance_mix",
     "rising_kappas",
+    "device_test_matrix",
 ]

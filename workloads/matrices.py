@@ -96,3 +96,22 @@ def rising_kappas(calls: int, lo_exp: float = 2.0, hi_exp: float = 14.0) -> np.n
     if calls == 1:
         return np.array([10.0 ** lo_exp])
     return 10.0 ** (lo_exp + (hi_exp - lo_exp) * np.arange(calls) / (calls - 1))
+
+
+def device_test_matrix(m: int, n: int, kappa: float, seed: int, device="cuda"):
+    """A = U diag(sigma) V^T drawn on the device, the family of test_matrix:
+    U from the QR of an m x n Gaussian drawn with torch's seeded generator on
+    the device, V orthonormal from a host Gaussian, sigma geometric from 1 to
+    1/kappa. Column-major float64 tensor. For large batches where building
+    every U on the host would take minutes."""
+    import torch
+
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    g = torch.randn(m, n, generator=gen, device=device, dtype=torch.float64)
+    u, _ = torch.linalg.qr(g)
+    v = _orthonormal_columns(_rng(seed), n, n)
+    w = torch.from_numpy(np.ascontiguousarray(singular_values(n, kappa)[:, None] * v.T)).to(device)  # diag(sigma) V^T
+    a = torch.empty((n, m), device=device, dtype=torch.float64).t()  # column-major
+    torch.mm(u, w, out=a)
+    return a
