@@ -42,8 +42,8 @@ hipError_t launch_ctrl_finalize(const Ctrl* ctrl, void* info, hipStream_t st);
 // grouped launches over the members of a batch
 hipError_t launch_draw_grouped(const BatchInst* bi, const int32_t* members, int count, int max_s,
                                const BatchCall& call, hipStream_t st);
-bool sketch_full_tiles(int n, int s);
-hipError_t launch_sketch_grouped(int prec, bool full, const BatchInst* bi, const int32_t* members, int count,
+int sketch_variant(int n, int s);
+hipError_t launch_sketch_grouped(int prec, int variant, const BatchInst* bi, const int32_t* members, int count,
                                  int max_chunks, int64_t max_ns, const BatchCall& call, int phase, hipStream_t st);
 int qr_group_key(bool f64, int s, int n);
 hipError_t launch_sketch_qr_grouped(bool f64, int key, const BatchInst* bi, const int32_t* members, int count,
@@ -53,8 +53,8 @@ int trsm_prep_elems(int n);
 hipError_t launch_trsm_grouped(int nmax, const BatchInst* bi, const int32_t* members, int count, int max_elems,
                                int max_blocks, const BatchCall& call, int phase, hipStream_t st);
 int gram_batch_chunks(int64_t m);
-bool syrk_full_tiles(int n);
-hipError_t launch_gram_grouped(bool full, const BatchInst* bi, const int32_t* members, int count, int max_chunks,
+int syrk_variant(int n);
+hipError_t launch_gram_grouped(int variant, const BatchInst* bi, const int32_t* members, int count, int max_chunks,
                                int max_n, const BatchCall& call, int phase, hipStream_t st);
 hipError_t launch_cholesky_grouped(const BatchInst* bi, const int32_t* members, int count, const BatchCall& call,
                                    int phase, hipStream_t st);
@@ -238,8 +238,8 @@ static int batch_plan_build(int32_t batch, const int64_t* m, const int64_t* n, m
     g64[k64].push_back(i);
     gtr[d.n <= 32 ? 32 : (d.n <= 64 ? 64 : 128)].push_back(i);
     gqf[(d.n + 15) / 16].push_back(i);
-    gsk[sketch_full_tiles(d.n, d.s) ? 1 : 0].push_back(i);
-    ggr[syrk_full_tiles(d.n) ? 1 : 0].push_back(i);
+    gsk[sketch_variant(d.n, d.s)].push_back(i);
+    ggr[syrk_variant(d.n)].push_back(i);
     p->max_s = std::max(p->max_s, d.s);
     p->max_n = std::max(p->max_n, d.n);
   }
@@ -292,7 +292,7 @@ static int batch_execute(const mrcqr_batch_plan* p, const BatchCall& call, hipSt
   bool ok = launch_draw_grouped(bi, all, nb, p->max_s, call, st) == hipSuccess;
   auto stage1 = [&](int pp, int phase) {
     for (const BatchGroup& g : p->sketch)
-      ok = ok && launch_sketch_grouped(pp, g.key == 1, bi, p->d_members + g.off, g.count, g.max_a, g.max_b, call, phase,
+      ok = ok && launch_sketch_grouped(pp, g.key, bi, p->d_members + g.off, g.count, g.max_a, g.max_b, call, phase,
                                        st) == hipSuccess;
     for (const BatchGroup& g : (pp == P_FP64 ? p->qr64 : p->qr32))
       ok = ok && launch_sketch_qr_grouped(pp == P_FP64, g.key, bi, p->d_members + g.off, g.count, g.max_a, call, pp,
@@ -303,7 +303,7 @@ static int batch_execute(const mrcqr_batch_plan* p, const BatchCall& call, hipSt
       ok = ok && launch_trsm_grouped(g.key, bi, p->d_members + g.off, g.count, g.max_a, g.max_b, call, phase, st) ==
                      hipSuccess;
     for (const BatchGroup& g : p->gram)
-      ok = ok && launch_gram_grouped(g.key == 1, bi, p->d_members + g.off, g.count, g.max_a, g.max_b, call, phase, st) ==
+      ok = ok && launch_gram_grouped(g.key, bi, p->d_members + g.off, g.count, g.max_a, g.max_b, call, phase, st) ==
                      hipSuccess;
     ok = ok && launch_cholesky_grouped(bi, all, nb, call, phase, st) == hipSuccess;
     ok = ok && launch_rc_tail_grouped(bi, all, nb, p->max_n, call, tail, st) == hipSuccess;

@@ -149,6 +149,111 @@ __device__ __forceinline__ void syrk_body(
   }
 }
 
+// n <= 16 NB with NB = 1, 2, 4: the panel holds only the 16 NB columns
+// that can exist, and the NB (NB + 1) / 2 upper tiles go to the waves in
+// order (wave w takes tiles w and w + 8). Every tile sees the same panels in
+// the same order, as the same MFMA sequence, as in syrk_body, so the
+// partial sums are bitwise the same; registers and LDS shrink with NB.
+template <int NB>
+__device__ __forceinline__ void syrk_small_body(
+    const double* __restrict__ B, int m, int n, int64_t ldb, int chunks,
+    double* __restrict__ Gpart, const Ctrl* __restrict__ ctrl, int phase) {
+  constexpr int NC = 16 * NB;              // columns staged
+  constexpr int NTILE = NB * (NB + 1) / 2;  // upper tiles
+  constexpr int TPW = (NTILE + 7) / 8;      // tiles per wave
+  __shared__ double tile[2][NC * GR_LDR];
+  if (skip_launch(ctrl, P_AUTO, phase)) return;
+  const int tid = threadIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63, g = l >> 4, c16 = l & 15;
+  const int nb = (n + 15) / 16;
+  const int64_t nslab = ((int64_t)m + GR_SLAB - 1) / GR_SLAB;
+  const int c = blockIdx.x;
+  const int nsc = (int)((nslab - c + chunks - 1) / chunks);
+  constexpr int PPS = GR_SLAB / GR_PANEL;
+  const int npan = nsc * PPS;
+  auto panel_row = [&](int i) -> int64_t {
+    const int64_t slab = c + (int64_t)chunks * (nsc - 1 - i / PPS);
+    return slab * GR_SLAB + (int64_t)GR_PANEL * (i % PPS);
+  };
+  const int64_t tend = m;
+
+  int ti[TPW], tj[TPW];
+  bool has[TPW];
+#pragma unroll
+  for (int u = 0; u < TPW; ++u) {
+    int t = w + 8 * u, I = 0;
+    has[u] = t < NTILE;
+    if (has[u]) {
+      while (t >= NB - I) { t -= NB - I; ++I; }
+    }
+    ti[u] = has[u] ? I : 0;
+    tj[u] = has[u] ? I + t : 0;
+    if (!(ti[u] < nb && tj[u] < nb)) { has[u] = false; ti[u] = 0; tj[u] = 0; }
+  }
+  f64x4 acc[TPW];
+#pragma unroll
+  for (int u = 0; u < TPW; ++u) acc[u] = f64x4{0, 0, 0, 0};
+
+  constexpr int CST = GR_THREADS / 64;           // column stride of a thread's columns
+  constexpr int EPT = NC / CST > 0 ? NC / CST : 1;  // columns per thread, one row
+  double regs[EPT];
+  auto load_panel = [&](int64_t t0) {
+    const int64_t t = t0 + l;
+    if (t0 + GR_PANEL <= tend && n == NC && NC >= CST) {
+      const double* bp = B + t + (int64_t)w * ldb;
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) regs[e] = bp[(int64_t)(CST * e) * ldb];
+    } else {
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const int col = w + CST * e;
+        regs[e] = (t < tend && col < n) ? B[t + (int64_t)col * ldb] : 0.0;
+      }
+    }
+  };
+  if (npan > 0) load_panel(panel_row(0));
+  for (int p = 0; p < npan; ++p) {
+    const int buf = p & 1;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int col = w + CST * e;
+      if (col < NC) tile[buf][col * GR_LDR + l] = regs[e];
+    }
+    if (p + 1 < npan) load_panel(panel_row(p + 1));
+    __syncthreads();
+    const double* tb = tile[buf] + c16 * GR_LDR + g;
+    if (has[0]) {
+#pragma unroll 4
+      for (int kk = 0; kk < GR_PANEL / 4; ++kk) {
+        const double* tk = tb + 4 * kk;
+#pragma unroll
+        for (int u = 0; u < TPW; ++u) {
+          if (!has[u]) continue;
+          const double a = tk[16 * ti[u] * GR_LDR], b = tk[16 * tj[u] * GR_LDR];
+          acc[u] = mfma_f64(a, b, acc[u]);
+        }
+      }
+    }
+  }
+  double* Gp = Gpart + (int64_t)blockIdx.x * n * n;
+#pragma unroll
+  for (int u = 0; u < TPW; ++u) {
+    if (!has[u]) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int col = 16 * tj[u] + c16, row = 16 * ti[u] + d_row_f64(l, r);
+      if (row < n && col < n) Gp[(int64_t)col * n + row] = acc[u][r];
+    }
+  }
+}
+
+template <int NB>
+__global__ __launch_bounds__(GR_THREADS) void syrk_small_kernel(
+    const double* __restrict__ B, int m, int n, int64_t ldb, int chunks,
+    double* __restrict__ Gpart, const Ctrl* __restrict__ ctrl, int phase) {
+  syrk_small_body<NB>(B, m, n, ldb, chunks, Gpart, ctrl, phase);
+}
+
 __global__ __launch_bounds__(GR_THREADS) void syrk_kernel(
     const double* __restrict__ B, int m, int n, int64_t ldb, int chunks,
     double* __restrict__ Gpart, const Ctrl* __restrict__ ctrl, int phase) {
@@ -172,6 +277,17 @@ __global__ __launch_bounds__(GR_THREADS) void syrk_grouped(const BatchInst* __re
   if ((int)blockIdx.x >= d.gram_chunks) return;
   syrk_body<FULL>(bat_ptr<const double>(call, d, d.off_B), d.m, d.n, d.m, d.gram_chunks,
                   bat_ptr<double>(call, d, d.off_Gpart), bat_ptr<const Ctrl>(call, d, d.off_ctrl), phase);
+}
+
+template <int NB>
+__global__ __launch_bounds__(GR_THREADS) void syrk_small_grouped(const BatchInst* __restrict__ bi,
+                                                                 const int32_t* __restrict__ members, BatchCall call,
+                                                                 int phase) {
+  const int i = bat_index(members);
+  const BatchInst& d = bi[i];
+  if ((int)blockIdx.x >= d.gram_chunks) return;
+  syrk_small_body<NB>(bat_ptr<const double>(call, d, d.off_B), d.m, d.n, d.m, d.gram_chunks,
+                      bat_ptr<double>(call, d, d.off_Gpart), bat_ptr<const Ctrl>(call, d, d.off_ctrl), phase);
 }
 
 // G[i, j] = G[j, i] = sum over chunks of the upper partial (i <= j). One
@@ -229,6 +345,15 @@ __global__ __launch_bounds__(256) void gram_reduce_grouped(const BatchInst* __re
                    d.n, bat_ptr<const Ctrl>(call, d, d.off_ctrl), phase);
 }
 
+// Kernel variant of the Gram of an n-column B: 0, 1, 2 = the small-n
+// kernel for n <= 16, 32, 64; 3 = skipped tiles past n; 4 = every tile.
+int syrk_variant(int n) {
+  if (n <= 16) return 0;
+  if (n <= 32) return 1;
+  if (n <= 64) return 2;
+  return n > GR_NMAX - 16 ? 4 : 3;
+}
+
 // one workgroup per compute unit, at most one per slab
 static int gram_chunks(int64_t m) {
   const int64_t nslab = (m + GR_SLAB - 1) / GR_SLAB;
@@ -237,12 +362,16 @@ static int gram_chunks(int64_t m) {
 
 int gram_batch_chunks(int64_t m) { return gram_chunks(m); }
 
-bool syrk_full_tiles(int n) { return n > GR_NMAX - 16; }
-
-hipError_t launch_gram_grouped(bool full, const BatchInst* bi, const int32_t* members, int count, int max_chunks,
+hipError_t launch_gram_grouped(int variant, const BatchInst* bi, const int32_t* members, int count, int max_chunks,
                                int max_n, const BatchCall& call, int phase, hipStream_t st) {
-  if (full) hipLaunchKernelGGL(syrk_grouped<true>, dim3(max_chunks, count), dim3(GR_THREADS), 0, st, bi, members, call, phase);
-  else hipLaunchKernelGGL(syrk_grouped<false>, dim3(max_chunks, count), dim3(GR_THREADS), 0, st, bi, members, call, phase);
+  const dim3 grid(max_chunks, count), block(GR_THREADS);
+  switch (variant) {
+    case 0: hipLaunchKernelGGL(syrk_small_grouped<1>, grid, block, 0, st, bi, members, call, phase); break;
+    case 1: hipLaunchKernelGGL(syrk_small_grouped<2>, grid, block, 0, st, bi, members, call, phase); break;
+    case 2: hipLaunchKernelGGL(syrk_small_grouped<4>, grid, block, 0, st, bi, members, call, phase); break;
+    case 3: hipLaunchKernelGGL(syrk_grouped<false>, grid, block, 0, st, bi, members, call, phase); break;
+    default: hipLaunchKernelGGL(syrk_grouped<true>, grid, block, 0, st, bi, members, call, phase); break;
+  }
   hipLaunchKernelGGL(gram_reduce_grouped, dim3(max_n, count), dim3(256), 0, st, bi, members, call, phase);
   return hipGetLastError();
 }
@@ -255,11 +384,14 @@ hipError_t launch_gram(const double* B, int m, int n, int64_t ldb, double* Gpart
                        const Ctrl* ctrl, int phase, hipStream_t st) {
   if (n > GR_NMAX) return hipErrorInvalidValue;
   const int chunks = gram_chunks(m);
-  if (syrk_full_tiles(n))  // every tile exists
-    hipLaunchKernelGGL(syrk_kernel, dim3(chunks), dim3(GR_THREADS), 0, st, B, m, n, ldb, chunks, Gpart, ctrl, phase);
-  else
-    hipLaunchKernelGGL(syrk_part_kernel, dim3(chunks), dim3(GR_THREADS), 0, st, B, m, n, ldb, chunks, Gpart, ctrl,
-                       phase);
+  const dim3 grid(chunks), block(GR_THREADS);
+  switch (syrk_variant(n)) {
+    case 0: hipLaunchKernelGGL(syrk_small_kernel<1>, grid, block, 0, st, B, m, n, ldb, chunks, Gpart, ctrl, phase); break;
+    case 1: hipLaunchKernelGGL(syrk_small_kernel<2>, grid, block, 0, st, B, m, n, ldb, chunks, Gpart, ctrl, phase); break;
+    case 2: hipLaunchKernelGGL(syrk_small_kernel<4>, grid, block, 0, st, B, m, n, ldb, chunks, Gpart, ctrl, phase); break;
+    case 3: hipLaunchKernelGGL(syrk_part_kernel, grid, block, 0, st, B, m, n, ldb, chunks, Gpart, ctrl, phase); break;
+    default: hipLaunchKernelGGL(syrk_kernel, grid, block, 0, st, B, m, n, ldb, chunks, Gpart, ctrl, phase); break;
+  }
   hipLaunchKernelGGL(gram_reduce_kernel, dim3(n), dim3(256), 0, st, (const double*)Gpart, chunks, n, G, ldg, ctrl, phase);
   return hipGetLastError();
 }

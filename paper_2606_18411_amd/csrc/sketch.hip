@@ -103,7 +103,7 @@ __device__ __forceinline__ uint32_t group8_max_u32_dpp(uint32_t v) {
   return v;
 }
 
-template <int P, bool FULL>
+template <int P, int NTL, bool FULL>
 __device__ __forceinline__ void sketch_body(
     const double* __restrict__ A, int64_t lda, int m, int n,
     const int32_t* __restrict__ S, int s, uint64_t seed, int rows_per_chunk,
@@ -119,8 +119,8 @@ __device__ __forceinline__ void sketch_body(
 
   if (skip_launch(ctrl, P, phase)) return;
 
-  __shared__ __attribute__((aligned(16))) elem tile[2][SK_NBLK * LD];
-  __shared__ float esc[2][SK_NBLK];
+  __shared__ __attribute__((aligned(16))) elem tile[2][16 * NTL * LD];
+  __shared__ float esc[2][16 * NTL];
   __shared__ uint64_t sgnm[2];
 
   const int tid = threadIdx.x;
@@ -131,8 +131,8 @@ __device__ __forceinline__ void sketch_body(
   // column tiles at or past n and M tiles of rows at or past s are skipped
   // (their products were zero and never stored; every stored sum goes
   // through the same products in the same order either way).
-  const int ncol = FULL ? SK_NBLK : min(n - cbase, SK_NBLK);
-  const int ntile = FULL ? 8 : (ncol + 15) >> 4;
+  const int ncol = FULL ? SK_NBLK : min(n - cbase, 16 * NTL);
+  const int ntile = FULL ? NTL : (ncol + 15) >> 4;
   const bool wload = FULL || w * 16 < ncol;  // this wave loads columns that exist
   bool mt_on[2];
 #pragma unroll
@@ -176,12 +176,12 @@ __device__ __forceinline__ void sketch_body(
 
   // ---- accumulators ----
   typedef typename std::conditional<LOWP, f32x4, f64x4>::type accv;
-  accv acc[2][8];
-  accv accp[2][8];
+  accv acc[2][NTL];
+  accv accp[2][NTL];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 8; ++b) { acc[a][b] = accv{0, 0, 0, 0}; accp[a][b] = accv{0, 0, 0, 0}; }
+    for (int b = 0; b < NTL; ++b) { acc[a][b] = accv{0, 0, 0, 0}; accp[a][b] = accv{0, 0, 0, 0}; }
 
   // ---- panel loader: thread covers columns cl_r = w*16 + r*8 + l/8 (r = 0,1),
   //      rows 8*(l%8) .. +7 of the panel ----
@@ -189,7 +189,7 @@ __device__ __forceinline__ void sketch_body(
   const int lrow = 8 * (l & 7);
   auto load_panel = [&](int64_t t0) {
     if (!wload) return;
-    if (t0 + SK_PANEL <= tend && cbase + SK_NBLK <= n) {
+    if (t0 + SK_PANEL <= tend && cbase + 16 * NTL <= n) {
 #pragma unroll
       for (int r = 0; r < 2; ++r) {
         const double* ap = A + t0 + lrow + (int64_t)(cbase + w * 16 + r * 8 + (l >> 3)) * lda;
@@ -288,9 +288,9 @@ __device__ __forceinline__ void sketch_body(
       typedef typename std::conditional<P == P_FP16, half8, bf16x8>::type vec8;
 #pragma unroll
       for (int ks = 0; ks < NKS; ++ks) {
-        vec8 bop[8];
+        vec8 bop[NTL];
 #pragma unroll
-        for (int nt = 0; nt < 8; ++nt)
+        for (int nt = 0; nt < NTL; ++nt)
           if (nt < ntile) bop[nt] = *reinterpret_cast<const vec8*>(&tb[(16 * nt + c16) * LD + KSTEP * ks + 8 * g]);
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt) {
@@ -313,7 +313,7 @@ __device__ __forceinline__ void sketch_body(
             aop[j] = (elem)ccur;
           }
 #pragma unroll
-          for (int nt = 0; nt < 8; ++nt) {
+          for (int nt = 0; nt < NTL; ++nt) {
             if (nt >= ntile) continue;
             const accv cin = (ks == 0) ? accv{0, 0, 0, 0} : accp[mt][nt];
             if constexpr (P == P_FP16) accp[mt][nt] = mfma_f16(aop, bop[nt], cin);
@@ -332,15 +332,15 @@ __device__ __forceinline__ void sketch_body(
       // 16 steps the base sits at the next panel's first row
 #pragma unroll
       for (int ks = 0; ks < NKS; ++ks) {
-        elem bop[8];
+        elem bop[NTL];
 #pragma unroll
-        for (int nt = 0; nt < 8; ++nt)
+        for (int nt = 0; nt < NTL; ++nt)
           if (nt < ntile) bop[nt] = tb[(16 * nt + c16) * LD + KSTEP * ks + g];
 #pragma unroll
         for (int mt = 0; mt < 2; ++mt) {
           const elem a = kvalid[mt] ? (elem)cb[mt] : (elem)0.0;
 #pragma unroll
-          for (int nt = 0; nt < 8; ++nt) {
+          for (int nt = 0; nt < NTL; ++nt) {
             if (!mt_on[mt] || nt >= ntile) continue;
             if constexpr (P == P_FP32) accp[mt][nt] = mfma_f32(a, bop[nt], accp[mt][nt]);
             else acc[mt][nt] = mfma_f64(a, bop[nt], acc[mt][nt]);
@@ -356,7 +356,7 @@ __device__ __forceinline__ void sketch_body(
     if constexpr (LOWP) {
       // undo the block prescale of this panel (one power of two per column)
 #pragma unroll
-      for (int nt = 0; nt < 8; ++nt) {
+      for (int nt = 0; nt < NTL; ++nt) {
         if (nt >= ntile) continue;
         const float sc = esc[buf][16 * nt + c16];
 #pragma unroll
@@ -374,7 +374,7 @@ __device__ __forceinline__ void sketch_body(
 #pragma unroll
   for (int mt = 0; mt < 2; ++mt)
 #pragma unroll
-    for (int nt = 0; nt < 8; ++nt) {
+    for (int nt = 0; nt < NTL; ++nt) {
       const int col = cbase + 16 * nt + c16;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -385,26 +385,27 @@ __device__ __forceinline__ void sketch_body(
     }
 }
 
-template <int P, bool FULL>
+template <int P, int NTL, bool FULL>
 __global__ __launch_bounds__(SK_THREADS) void sketch_kernel(
     const double* __restrict__ A, int64_t lda, int m, int n,
     const int32_t* __restrict__ S, int s, uint64_t seed, int rows_per_chunk,
     typename SkT<P>::acc* __restrict__ Ypart, const Ctrl* __restrict__ ctrl, int phase) {
-  sketch_body<P, FULL>(A, lda, m, n, S, s, seed, rows_per_chunk, Ypart, ctrl, phase, blockIdx.x, blockIdx.y, blockIdx.z);
+  sketch_body<P, NTL, FULL>(A, lda, m, n, S, s, seed, rows_per_chunk, Ypart, ctrl, phase, blockIdx.x, blockIdx.y,
+                            blockIdx.z);
 }
 
 // Grouped (members with n <= 128 and s <= 256: one column block and one
 // sketch-row block each); blockIdx.x is the row chunk. Members are grouped
 // by the variant a single call of their shape uses (FULL when n = 128 and
 // s = 256), since the two may round the coefficients differently.
-template <int P, bool FULL>
+template <int P, int NTL, bool FULL>
 __global__ __launch_bounds__(SK_THREADS) void sketch_grouped(const BatchInst* __restrict__ bi,
                                                              const int32_t* __restrict__ members, BatchCall call,
                                                              int phase) {
   const int i = bat_index(members);
   const BatchInst& d = bi[i];
   if ((int)blockIdx.x >= d.sk_chunks) return;
-  sketch_body<P, FULL>(call.A[i], call.lda[i], d.m, d.n, bat_ptr<int32_t>(call, d, d.off_S), d.s, call.seed[i],
+  sketch_body<P, NTL, FULL>(call.A[i], call.lda[i], d.m, d.n, bat_ptr<int32_t>(call, d, d.off_S), d.s, call.seed[i],
                        d.sk_rows, bat_ptr<typename SkT<P>::acc>(call, d, d.off_Ypart),
                        bat_ptr<Ctrl>(call, d, d.off_ctrl), phase, blockIdx.x, 0, 0);
 }
@@ -471,9 +472,43 @@ __global__ __launch_bounds__(256) void sketch_reduce_grouped(const BatchInst* __
 // ---- host-side launch -------------------------------------------------
 struct SketchGeom { int chunks, rows_per_chunk; };
 
-// every block of an (n, s) sketch covers 128 existing columns and 256
-// existing sketch rows
-bool sketch_full_tiles(int n, int s) { return n % SK_NBLK == 0 && s % SK_SBLK == 0; }
+// Kernel variant of an (n, s) sketch: the column tiles a block holds in
+// registers and LDS (NTL = 1, 2, 4 for n <= 16, 32, 64, else 8), and FULL
+// when every block covers 128 existing columns and 256 existing sketch rows.
+// variant = 0, 1, 2 (NTL = 1, 2, 4), 3 (NTL = 8), 4 (NTL = 8, FULL).
+int sketch_variant(int n, int s) {
+  if (n <= 16) return 0;
+  if (n <= 32) return 1;
+  if (n <= 64) return 2;
+  return (n % SK_NBLK == 0 && s % SK_SBLK == 0) ? 4 : 3;
+}
+
+template <int P>
+static void launch_sketch_v(int v, dim3 grid, hipStream_t st, const double* A, int64_t lda, int m, int n,
+                            const int32_t* S, int s, uint64_t seed, int rows_per_chunk, typename SkT<P>::acc* Ypart,
+                            const Ctrl* ctrl, int phase) {
+  const dim3 block(SK_THREADS);
+  switch (v) {
+    case 0: hipLaunchKernelGGL((sketch_kernel<P, 1, false>), grid, block, 0, st, A, lda, m, n, S, s, seed, rows_per_chunk, Ypart, ctrl, phase); break;
+    case 1: hipLaunchKernelGGL((sketch_kernel<P, 2, false>), grid, block, 0, st, A, lda, m, n, S, s, seed, rows_per_chunk, Ypart, ctrl, phase); break;
+    case 2: hipLaunchKernelGGL((sketch_kernel<P, 4, false>), grid, block, 0, st, A, lda, m, n, S, s, seed, rows_per_chunk, Ypart, ctrl, phase); break;
+    case 3: hipLaunchKernelGGL((sketch_kernel<P, 8, false>), grid, block, 0, st, A, lda, m, n, S, s, seed, rows_per_chunk, Ypart, ctrl, phase); break;
+    default: hipLaunchKernelGGL((sketch_kernel<P, 8, true>), grid, block, 0, st, A, lda, m, n, S, s, seed, rows_per_chunk, Ypart, ctrl, phase); break;
+  }
+}
+
+template <int P>
+static void launch_sketch_grouped_v(int v, dim3 grid, hipStream_t st, const BatchInst* bi, const int32_t* members,
+                                    const BatchCall& call, int phase) {
+  const dim3 block(SK_THREADS);
+  switch (v) {
+    case 0: hipLaunchKernelGGL((sketch_grouped<P, 1, false>), grid, block, 0, st, bi, members, call, phase); break;
+    case 1: hipLaunchKernelGGL((sketch_grouped<P, 2, false>), grid, block, 0, st, bi, members, call, phase); break;
+    case 2: hipLaunchKernelGGL((sketch_grouped<P, 4, false>), grid, block, 0, st, bi, members, call, phase); break;
+    case 3: hipLaunchKernelGGL((sketch_grouped<P, 8, false>), grid, block, 0, st, bi, members, call, phase); break;
+    default: hipLaunchKernelGGL((sketch_grouped<P, 8, true>), grid, block, 0, st, bi, members, call, phase); break;
+  }
+}
 
 SketchGeom sketch_geometry(int64_t m) {
   const int64_t npan = (m + SK_PANEL - 1) / SK_PANEL;
@@ -499,27 +534,23 @@ hipError_t launch_sketch(int prec, const double* A, int64_t lda, int m, int n, c
   dim3 block(SK_THREADS);
   const int rb = 256;
   const int64_t tot = (int64_t)n * s;
-  const bool full = sketch_full_tiles(n, s);  // every block's tile exists whole
+  const int v = sketch_variant(n, s);
   dim3 rgrid((unsigned)((tot + 63) / 64));
   switch (prec) {
     case P_FP16:
-      if (full) hipLaunchKernelGGL((sketch_kernel<P_FP16, true>), grid, block, 0, st, A, lda, m, n, S, s, seed, gg.rows_per_chunk, (float*)Ypart, ctrl, phase);
-      else hipLaunchKernelGGL((sketch_kernel<P_FP16, false>), grid, block, 0, st, A, lda, m, n, S, s, seed, gg.rows_per_chunk, (float*)Ypart, ctrl, phase);
+      launch_sketch_v<P_FP16>(v, grid, st, A, lda, m, n, S, s, seed, gg.rows_per_chunk, (float*)Ypart, ctrl, phase);
       hipLaunchKernelGGL(sketch_reduce_kernel<float>, rgrid, dim3(rb), 0, st, (const float*)Ypart, gg.chunks, n, s, S, Y, ldy, 1, ctrl, (int)P_FP16, phase);
       break;
     case P_BF16:
-      if (full) hipLaunchKernelGGL((sketch_kernel<P_BF16, true>), grid, block, 0, st, A, lda, m, n, S, s, seed, gg.rows_per_chunk, (float*)Ypart, ctrl, phase);
-      else hipLaunchKernelGGL((sketch_kernel<P_BF16, false>), grid, block, 0, st, A, lda, m, n, S, s, seed, gg.rows_per_chunk, (float*)Ypart, ctrl, phase);
+      launch_sketch_v<P_BF16>(v, grid, st, A, lda, m, n, S, s, seed, gg.rows_per_chunk, (float*)Ypart, ctrl, phase);
       hipLaunchKernelGGL(sketch_reduce_kernel<float>, rgrid, dim3(rb), 0, st, (const float*)Ypart, gg.chunks, n, s, S, Y, ldy, 1, ctrl, (int)P_BF16, phase);
       break;
     case P_FP32:
-      if (full) hipLaunchKernelGGL((sketch_kernel<P_FP32, true>), grid, block, 0, st, A, lda, m, n, S, s, seed, gg.rows_per_chunk, (float*)Ypart, ctrl, phase);
-      else hipLaunchKernelGGL((sketch_kernel<P_FP32, false>), grid, block, 0, st, A, lda, m, n, S, s, seed, gg.rows_per_chunk, (float*)Ypart, ctrl, phase);
+      launch_sketch_v<P_FP32>(v, grid, st, A, lda, m, n, S, s, seed, gg.rows_per_chunk, (float*)Ypart, ctrl, phase);
       hipLaunchKernelGGL(sketch_reduce_kernel<float>, rgrid, dim3(rb), 0, st, (const float*)Ypart, gg.chunks, n, s, S, Y, ldy, 1, ctrl, (int)P_FP32, phase);
       break;
     case P_FP64:
-      if (full) hipLaunchKernelGGL((sketch_kernel<P_FP64, true>), grid, block, 0, st, A, lda, m, n, S, s, seed, gg.rows_per_chunk, (double*)Ypart, ctrl, phase);
-      else hipLaunchKernelGGL((sketch_kernel<P_FP64, false>), grid, block, 0, st, A, lda, m, n, S, s, seed, gg.rows_per_chunk, (double*)Ypart, ctrl, phase);
+      launch_sketch_v<P_FP64>(v, grid, st, A, lda, m, n, S, s, seed, gg.rows_per_chunk, (double*)Ypart, ctrl, phase);
       hipLaunchKernelGGL(sketch_reduce_kernel<double>, rgrid, dim3(rb), 0, st, (const double*)Ypart, gg.chunks, n, s, S, Y, ldy, 0, ctrl, (int)P_FP64, phase);
       break;
     default:
@@ -530,28 +561,24 @@ hipError_t launch_sketch(int prec, const double* A, int64_t lda, int m, int n, c
 
 // Stage 1's sketch for every member of a batch at precision prec: grid
 // (largest chunk count, members), then the reduction.
-hipError_t launch_sketch_grouped(int prec, bool full, const BatchInst* bi, const int32_t* members, int count,
+hipError_t launch_sketch_grouped(int prec, int variant, const BatchInst* bi, const int32_t* members, int count,
                                  int max_chunks, int64_t max_ns, const BatchCall& call, int phase, hipStream_t st) {
   const dim3 grid(max_chunks, count), rgrid((unsigned)((max_ns + 63) / 64), count);
   switch (prec) {
     case P_FP16:
-      if (full) hipLaunchKernelGGL((sketch_grouped<P_FP16, true>), grid, dim3(SK_THREADS), 0, st, bi, members, call, phase);
-      else hipLaunchKernelGGL((sketch_grouped<P_FP16, false>), grid, dim3(SK_THREADS), 0, st, bi, members, call, phase);
+      launch_sketch_grouped_v<P_FP16>(variant, grid, st, bi, members, call, phase);
       hipLaunchKernelGGL(sketch_reduce_grouped<float>, rgrid, dim3(256), 0, st, bi, members, call, 1, (int)P_FP16, phase);
       break;
     case P_BF16:
-      if (full) hipLaunchKernelGGL((sketch_grouped<P_BF16, true>), grid, dim3(SK_THREADS), 0, st, bi, members, call, phase);
-      else hipLaunchKernelGGL((sketch_grouped<P_BF16, false>), grid, dim3(SK_THREADS), 0, st, bi, members, call, phase);
+      launch_sketch_grouped_v<P_BF16>(variant, grid, st, bi, members, call, phase);
       hipLaunchKernelGGL(sketch_reduce_grouped<float>, rgrid, dim3(256), 0, st, bi, members, call, 1, (int)P_BF16, phase);
       break;
     case P_FP32:
-      if (full) hipLaunchKernelGGL((sketch_grouped<P_FP32, true>), grid, dim3(SK_THREADS), 0, st, bi, members, call, phase);
-      else hipLaunchKernelGGL((sketch_grouped<P_FP32, false>), grid, dim3(SK_THREADS), 0, st, bi, members, call, phase);
+      launch_sketch_grouped_v<P_FP32>(variant, grid, st, bi, members, call, phase);
       hipLaunchKernelGGL(sketch_reduce_grouped<float>, rgrid, dim3(256), 0, st, bi, members, call, 1, (int)P_FP32, phase);
       break;
     case P_FP64:
-      if (full) hipLaunchKernelGGL((sketch_grouped<P_FP64, true>), grid, dim3(SK_THREADS), 0, st, bi, members, call, phase);
-      else hipLaunchKernelGGL((sketch_grouped<P_FP64, false>), grid, dim3(SK_THREADS), 0, st, bi, members, call, phase);
+      launch_sketch_grouped_v<P_FP64>(variant, grid, st, bi, members, call, phase);
       hipLaunchKernelGGL(sketch_reduce_grouped<double>, rgrid, dim3(256), 0, st, bi, members, call, 0, (int)P_FP64, phase);
       break;
     default:
