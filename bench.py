@@ -13,6 +13,7 @@ The dominant kernel's launches are timed with HIP events on the library's
 stream for the roofline figure. The CPU oracle is timed on a row sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+       python bench.py --workload uneven_batch   (512 uneven QRs as one batch)
 """
 from __future__ import annotations
 
@@ -56,6 +57,55 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def bench_uneven_batch(args) -> int:
+    """512 members, m uniform in [4096, 131072], n in {8, 16, 32, 64}, kappa
+    log-uniform in [1e2, 1e12], A = U diag(sigma) V^T drawn on the device,
+    AUTO precision per member, one batch = one grouped-launch execution."""
+    import torch
+    import paper_2606_18411_amd as M
+    import workloads as W
+
+    M.lib()
+    torch.cuda.set_device(0)
+    mix = W.instance_mix(512, 2024)
+    log("drawing the 512 members on the device")
+    As = [W.device_test_matrix(m, n, k, 4000 + i) for i, (m, n, k) in enumerate(mix)]
+    shapes = [(m, n) for m, n, _ in mix]
+    bp = M.BatchPlan(shapes)
+    Qs = [M.empty_colmajor(m, n) for m, n in shapes]
+    Rs = [M.empty_colmajor(n, n) for _, n in shapes]
+    bp.bind(As, Qs, Rs, "auto", list(range(1, len(mix) + 1)))
+    for _ in range(args.warmup):
+        bp.execute()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.steps):
+        bp.execute()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    infos = bp.last_infos()
+    ok = sum(i.status == 0 for i in infos)
+    # algorithmic HBM bytes: one read of A per sketch attempt, then read A and
+    # write B (solve), read B (Gram), read B and write Q (product)
+    nbytes = sum(8.0 * m * n * (1 + inf.escalations + 5) for (m, n), inf in zip(shapes, infos))
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    pr = [i.precision for i in infos]
+    out = {
+        "metric": "ms per batch of 512 uneven QRs (m in [4096,131072], n in {8,16,32,64}, kappa 1e2..1e12, AUTO)",
+        "value": round(ms, 4), "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 4), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 (sketch per member: f16/f32/f64)", "data": "synthetic",
+        "config": {"workload": "uneven batch, 512 members, grouped launches", "members": len(mix),
+                   "status_ok": ok, "precisions": {p: pr.count(p) for p in ("fp16", "fp32", "fp64")}},
+        "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None},
+    }
+    print(json.dumps(out), flush=True)
+    return 0 if ok == len(mix) else 1
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,11 +118,15 @@ def main() -> int:
     ap.add_argument("--cpu-sample-rows", type=int, default=1 << 20)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 256 MiB device copy first (reference for the HBM byte counters)")
+    ap.add_argument("--workload", choices=["headline", "uneven_batch"], default="headline",
+                    help="uneven_batch: 512 uneven factorizations as one batch (grouped launches)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the factorization of one matrix "
               "is a single-GPU workload here", file=sys.stderr)
         return 2
+    if args.workload == "uneven_batch":
+        return bench_uneven_batch(args)
 
     import torch
     import paper_2606_18411_amd as M
