@@ -4,8 +4,9 @@
 // C_S[i, t] = cos(pi (2t+1) S[i] / (2m)) are generated on the fly.
 //
 // Work decomposition: grid (row chunks, column blocks of 128, sketch-row
-// blocks of 256). A workgroup of 8 waves streams its row chunk in panels of
-// 64 rows: the panel is loaded once (coalesced, 512 B per column), signed,
+// blocks of 256). A workgroup of 8 waves (for n <= 16, 32, 64: 1, 2, 4
+// waves, 16 columns and 32 sketch rows each, so that no wave idles) streams
+// its row chunk in panels of 64 rows: the panel is loaded once (coalesced, 512 B per column), signed,
 // block-prescaled and cast, and written to LDS in the layout of the MFMA B
 // operand; each wave generates the coefficients of its 32 sketch rows
 // straight into A-operand registers and multiplies against the whole panel.
@@ -23,7 +24,6 @@
 
 namespace mrcqr {
 
-constexpr int SK_THREADS = 512;
 constexpr int SK_SBLK = 256;
 constexpr int SK_NBLK = 128;
 constexpr int SK_PANEL = 64;
@@ -126,7 +126,9 @@ __device__ __forceinline__ void sketch_body(
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63, g = l >> 4, c16 = l & 15;
   const int cbase = cblk * SK_NBLK;
-  const int sbase = sblk * SK_SBLK + w * 32;
+  // NTL waves per block: wave w loads columns 16 w .. 16 w + 15 of the panel
+  // and owns sketch rows 32 w .. 32 w + 31 of the block's 32 NTL rows
+  const int sbase = sblk * (32 * NTL) + w * 32;
   // FULL: the block's 128 columns and 256 sketch rows all exist. Otherwise
   // column tiles at or past n and M tiles of rows at or past s are skipped
   // (their products were zero and never stored; every stored sum goes
@@ -386,7 +388,7 @@ __device__ __forceinline__ void sketch_body(
 }
 
 template <int P, int NTL, bool FULL>
-__global__ __launch_bounds__(SK_THREADS) void sketch_kernel(
+__global__ __launch_bounds__(64 * NTL) void sketch_kernel(
     const double* __restrict__ A, int64_t lda, int m, int n,
     const int32_t* __restrict__ S, int s, uint64_t seed, int rows_per_chunk,
     typename SkT<P>::acc* __restrict__ Ypart, const Ctrl* __restrict__ ctrl, int phase) {
@@ -399,7 +401,7 @@ __global__ __launch_bounds__(SK_THREADS) void sketch_kernel(
 // by the variant a single call of their shape uses (FULL when n = 128 and
 // s = 256), since the two may round the coefficients differently.
 template <int P, int NTL, bool FULL>
-__global__ __launch_bounds__(SK_THREADS) void sketch_grouped(const BatchInst* __restrict__ bi,
+__global__ __launch_bounds__(64 * NTL) void sketch_grouped(const BatchInst* __restrict__ bi,
                                                              const int32_t* __restrict__ members, BatchCall call,
                                                              int phase) {
   const int i = bat_index(members);
@@ -483,11 +485,14 @@ int sketch_variant(int n, int s) {
   return (n % SK_NBLK == 0 && s % SK_SBLK == 0) ? 4 : 3;
 }
 
+// waves per block (= column tiles held) of a variant
+static int sketch_waves(int v) { return v == 0 ? 1 : v == 1 ? 2 : v == 2 ? 4 : 8; }
+
 template <int P>
 static void launch_sketch_v(int v, dim3 grid, hipStream_t st, const double* A, int64_t lda, int m, int n,
                             const int32_t* S, int s, uint64_t seed, int rows_per_chunk, typename SkT<P>::acc* Ypart,
                             const Ctrl* ctrl, int phase) {
-  const dim3 block(SK_THREADS);
+  const dim3 block(64 * sketch_waves(v));
   switch (v) {
     case 0: hipLaunchKernelGGL((sketch_kernel<P, 1, false>), grid, block, 0, st, A, lda, m, n, S, s, seed, rows_per_chunk, Ypart, ctrl, phase); break;
     case 1: hipLaunchKernelGGL((sketch_kernel<P, 2, false>), grid, block, 0, st, A, lda, m, n, S, s, seed, rows_per_chunk, Ypart, ctrl, phase); break;
@@ -500,7 +505,7 @@ static void launch_sketch_v(int v, dim3 grid, hipStream_t st, const double* A, i
 template <int P>
 static void launch_sketch_grouped_v(int v, dim3 grid, hipStream_t st, const BatchInst* bi, const int32_t* members,
                                     const BatchCall& call, int phase) {
-  const dim3 block(SK_THREADS);
+  const dim3 block(64 * sketch_waves(v));
   switch (v) {
     case 0: hipLaunchKernelGGL((sketch_grouped<P, 1, false>), grid, block, 0, st, bi, members, call, phase); break;
     case 1: hipLaunchKernelGGL((sketch_grouped<P, 2, false>), grid, block, 0, st, bi, members, call, phase); break;
@@ -530,11 +535,11 @@ hipError_t launch_sketch(int prec, const double* A, int64_t lda, int m, int n, c
                          uint64_t seed, void* Ypart, double* Y, int64_t ldy, const Ctrl* ctrl, int phase,
                          hipStream_t st) {
   SketchGeom gg = sketch_geometry(m);
-  dim3 grid(gg.chunks, (n + SK_NBLK - 1) / SK_NBLK, (s + SK_SBLK - 1) / SK_SBLK);
-  dim3 block(SK_THREADS);
+  const int v = sketch_variant(n, s);
+  const int srows = 32 * sketch_waves(v);  // sketch rows per block
+  dim3 grid(gg.chunks, (n + SK_NBLK - 1) / SK_NBLK, (s + srows - 1) / srows);
   const int rb = 256;
   const int64_t tot = (int64_t)n * s;
-  const int v = sketch_variant(n, s);
   dim3 rgrid((unsigned)((tot + 63) / 64));
   switch (prec) {
     case P_FP16:
