@@ -81,3 +81,40 @@ def test_plan_workspace_layout_is_sane(lib):
     assert (1 << 20) * 128 * 8 < b < (1 << 20) * 128 * 8 * 1.5  # B dominates the workspace
     lib.mrcqr_plan_destroy(p)
     assert lib.mrcqr_plan_create(10, 20, 0, ctypes.byref(p)) == 1
+
+
+def test_batch_and_regime_argument_errors(lib):
+    """The batch plan rejects bad member shapes, and the batch and regime
+    entry points reject missing arguments, before any device call."""
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    vp = ctypes.c_void_p
+    lib.mrcqr_batch_plan_create.argtypes = [ctypes.c_int32, i64p, i64p, ctypes.POINTER(vp)]
+    lib.mrcqr_batch_plan_create.restype = ctypes.c_int
+    arr = lambda vals: (ctypes.c_int64 * len(vals))(*vals)
+    p = vp()
+    cases = [((), (), 1),                         # empty batch
+             ((100, 64), (10, 40), 1),            # member 1: s = 2n > m
+             ((1000, 1000), (10, 200), 8),        # member 1: n above this build's limit
+             ((1000,), (0,), 1),                  # n = 0
+             ((1 << 28,), (4,), 8)]               # m beyond the exact-phase row limit
+    for ms, ns, want in cases:
+        k = len(ms)
+        got = lib.mrcqr_batch_plan_create(k, arr(ms) if k else None, arr(ns) if k else None, ctypes.byref(p))
+        assert got == want, (ms, ns, got)
+    assert lib.mrcqr_batch_plan_create(1, arr([100]), arr([10]), None) == 1  # no output pointer
+    lib.mrcqr_batch_plan_workspace_bytes.restype = ctypes.c_size_t
+    lib.mrcqr_batch_plan_workspace_bytes.argtypes = [vp]
+    assert lib.mrcqr_batch_plan_workspace_bytes(None) == 0
+    lib.mrcqr_batch_execute.argtypes = [vp] * 2 + [ctypes.c_size_t] + [vp] * 10
+    lib.mrcqr_batch_execute.restype = ctypes.c_int
+    assert lib.mrcqr_batch_execute(None, None, 0, *([None] * 10)) == 1
+    lib.mrcqr_regime_reset.argtypes = [vp, vp, ctypes.c_size_t, vp]
+    lib.mrcqr_regime_reset.restype = ctypes.c_int
+    assert lib.mrcqr_regime_reset(None, None, 0, None) == 1
+    # a plan without a workspace: MRCQR_ERR_WORKSPACE
+    q = vp()
+    lib.mrcqr_plan_create.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(vp)]
+    assert lib.mrcqr_plan_create(4096, 32, 0, ctypes.byref(q)) == 0
+    assert lib.mrcqr_regime_reset(q, None, 0, None) == 5
+    lib.mrcqr_plan_destroy.argtypes = [vp]
+    lib.mrcqr_plan_destroy(q)
