@@ -207,6 +207,10 @@ class Plan:
             pass
 
 
+def _as_int64(u: int) -> int:
+    return u - 2 ** 64 if u >= 2 ** 63 else u
+
+
 class BatchPlan:
     """A batch of independent factorizations of shapes [(m, n), ...] (s = 2n),
     run as grouped launches; execute() allocates nothing once the per-member
@@ -235,7 +239,7 @@ class BatchPlan:
         self._args = (
             i64([a.data_ptr() for a in As]), i64([_ld(a) for a in As]),
             torch.tensor([_prec(q) for q in precs], dtype=torch.int32, device=dev),
-            i64([int(x) & (2 ** 63 - 1) if int(x) < 2 ** 63 else int(x) - 2 ** 64 for x in seeds]),
+            i64([_as_int64(int(x) & (2 ** 64 - 1)) for x in seeds]),  # uint64 bits in an int64 tensor
             i64([q.data_ptr() for q in Qs]), i64([_ld(q) for q in Qs]),
             i64([r.data_ptr() for r in Rs]), i64([_ld(r) for r in Rs]),
             (As, Qs, Rs),

@@ -482,10 +482,12 @@ int mrcqr_factor_batched(int32_t batch, const double* const* A, const int64_t* m
                  reinterpret_cast<const int32_t*>(d + 7 * b8), reinterpret_cast<const uint64_t*>(d + 6 * b8),
                  infos_dev};
   const int c = batch_execute(be.plan, call, as_stream(stream));
+  // recorded even after a failed launch: the kernels enqueued before it may
+  // still read the argument arrays, and the next call waits for them
+  const bool recorded = hipEventRecord(be.done, as_stream(stream)) == hipSuccess;
+  be.used = recorded;
   if (c) return c;
-  if (hipEventRecord(be.done, as_stream(stream)) != hipSuccess) return MRCQR_ERR_DEVICE;
-  be.used = true;
-  return MRCQR_OK;
+  return recorded ? MRCQR_OK : MRCQR_ERR_DEVICE;
 }
 
 int mrcqr_draw(uint64_t seed, int64_t m, int64_t s, int32_t* S_dev, int8_t* D_dev, void* stream) {

@@ -11,7 +11,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-enum Prec : int { P_AUTO = 0, P_FP64 = 1, P_FP32 = 2, P_FP16 = 3, P_BF16 = 4 };
+enum Prec : int { P_AUTO = 0, P_FP64 = 1, P_FP32 = 2, P_FP16 = 3, P_BF16 = 4, P_AUTO_CARRY = 5 };
 
 // MFMA lane layouts on gfx950 (16x16xK, wave64), checked on the device:
 //   A operand (16 x K): lane l holds A[l % 16][(l / 16) * (K / 4) + j], j < K/4

@@ -124,16 +124,16 @@ __global__ __launch_bounds__(DRAW_THREADS) void draw_grouped(const BatchInst* __
   const int i = bat_index(members);
   const BatchInst& d = bi[i];
   const int p = call.prec[i];
-  const bool am = p == P_AUTO || p == 5;
+  const bool am = p == P_AUTO || p == P_AUTO_CARRY;
   Ctrl* ctrl = bat_ptr<Ctrl>(call, d, d.off_ctrl);
   draw_body(call.seed[i], d.m, d.s, bat_ptr<int32_t>(call, d, d.off_S), ctrl, am ? P_FP16 : p,
-            p == 5 ? AM_CARRY : am ? AM_AUTO : AM_FIXED);
+            p == P_AUTO_CARRY ? AM_CARRY : am ? AM_AUTO : AM_FIXED);
   // the per-call arguments live in device memory: checked here, and a
   // member that fails is skipped by every later kernel of the batch
   if (threadIdx.x == 0) {
     const bool ok = call.A[i] != nullptr && call.Q[i] != nullptr && call.R[i] != nullptr &&
                     call.A[i] != call.Q[i] && call.lda[i] >= d.m && call.ldq[i] >= d.m && call.ldr[i] >= d.n &&
-                    p >= 0 && p <= 5;
+                    p >= P_AUTO && p <= P_AUTO_CARRY;
     if (!ok) ctrl->status = ST_ARG;
   }
 }
