@@ -292,7 +292,7 @@ __device__ __forceinline__ void qform_body(
 }
 
 template <int NB, int NT>
-__global__ __launch_bounds__(NT == 2 ? 256 : 512) void qform_kernel(
+__global__ __launch_bounds__(NT == 2 ? 256 : 512, NB <= 2 ? 4 : 1) void qform_kernel(
     const double* __restrict__ B, int m, int n, int64_t ldb, const double* __restrict__ X, int64_t ldx,
     double* __restrict__ Q, int64_t ldq, const Ctrl* __restrict__ ctrl, int phase) {
   qform_body<NB, NT>(B, m, n, ldb, X, ldx, Q, ldq, ctrl, phase, blockIdx.x, gridDim.x);
@@ -300,7 +300,7 @@ __global__ __launch_bounds__(NT == 2 ? 256 : 512) void qform_kernel(
 
 // Grouped: Q = B X of each member; a member uses its own block count.
 template <int NB, int NT>
-__global__ __launch_bounds__(NT == 2 ? 256 : 512) void qform_grouped(const BatchInst* __restrict__ bi,
+__global__ __launch_bounds__(NT == 2 ? 256 : 512, NB <= 2 ? 4 : 1) void qform_grouped(const BatchInst* __restrict__ bi,
                                                                      const int32_t* __restrict__ members,
                                                                      BatchCall call, int phase) {
   const int i = bat_index(members);
@@ -363,7 +363,9 @@ hipError_t launch_qform(const double* B, int m, int n, int64_t ldb, const double
   constexpr int NT = QF_NT;
   constexpr int rows = (NT == 2 ? 256 : 512) / 64 * 16 * NT;
   const int64_t npass = ((int64_t)m + rows - 1) / rows;
-  const int grid = (int)(npass < 256 ? npass : 256);  // one workgroup per CU
+  // one workgroup per CU per wave the instance fits on a SIMD (4 at n <= 32)
+  const int64_t cap = 256 * (n <= 32 ? 4 : 1);
+  const int grid = (int)(npass < cap ? npass : cap);
   if (grid < 1) return hipGetLastError();
   const int nb = (n + 15) / 16;
   const dim3 block(NT == 2 ? 256 : 512);

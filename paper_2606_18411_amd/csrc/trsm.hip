@@ -170,7 +170,7 @@ __device__ __forceinline__ void trsm_body(
 }
 
 template <int NMAX>
-__global__ __launch_bounds__(TR_THREADS) void trsm_kernel(
+__global__ __launch_bounds__(TR_THREADS, NMAX == 64 ? 2 : (NMAX == 32 ? 4 : 1)) void trsm_kernel(
     const double* __restrict__ A, int m, int n, int64_t lda,
     const double* __restrict__ Rop, const double* __restrict__ Dg,
     double* __restrict__ X, int64_t ldx, const Ctrl* __restrict__ ctrl, int phase) {
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(TR_THREADS) void trsm_kernel(
 
 // Grouped: B = A Rs^{-1} of each member; a member uses its own block count.
 template <int NMAX>
-__global__ __launch_bounds__(TR_THREADS) void trsm_grouped(const BatchInst* __restrict__ bi,
+__global__ __launch_bounds__(TR_THREADS, NMAX == 64 ? 2 : (NMAX == 32 ? 4 : 1)) void trsm_grouped(const BatchInst* __restrict__ bi,
                                                            const int32_t* __restrict__ members, BatchCall call,
                                                            int phase) {
   const int i = bat_index(members);
@@ -226,7 +226,10 @@ hipError_t launch_trsm(const double* A, int m, int n, int64_t lda, const double*
   hipLaunchKernelGGL(trsm_prep_kernel, dim3((prep_elems + 255) / 256), dim3(256), 0, st, R, n, ldr, Rop, Dg,
                      ctrl, phase);
   const int64_t panels = ((int64_t)m + TR_ROWS - 1) / TR_ROWS;
-  const int grid = (int)(panels < 256 ? panels : 256);  // one workgroup per CU (LDS-bound)
+  // one workgroup per CU per wave the instance fits on a SIMD (1 at n > 64,
+  // 2 at n <= 64, 4 at n <= 32: see the launch bounds)
+  const int64_t cap = 256 * (n <= 32 ? 4 : (n <= 64 ? 2 : 1));
+  const int grid = (int)(panels < cap ? panels : cap);
   if (grid < 1) return hipGetLastError();
   if (n <= 32) hipLaunchKernelGGL(trsm_kernel<32>, dim3(grid), dim3(TR_THREADS), 0, st, A, m, n, lda, Rop, Dg, X, ldx, ctrl, phase);
   else if (n <= 64) hipLaunchKernelGGL(trsm_kernel<64>, dim3(grid), dim3(TR_THREADS), 0, st, A, m, n, lda, Rop, Dg, X, ldx, ctrl, phase);
