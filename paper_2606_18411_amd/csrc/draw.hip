@@ -12,7 +12,6 @@ namespace mrcqr {
 
 constexpr int DRAW_THREADS = 1024;
 constexpr int DRAW_SMAX = 2048;           // largest supported s
-constexpr int DRAW_SLOTS = DRAW_SMAX / 64;
 
 __device__ __forceinline__ uint32_t floyd_r(uint64_t key1, uint64_t j) {
   return (uint32_t)__umul64hi(hash_at(key1, j), j + 1);
@@ -79,33 +78,55 @@ __device__ __forceinline__ void draw_body(uint64_t seed, int m, int s, int32_t* 
     if (keys[i] == keys[i + 1]) dup = 1;
   __syncthreads();
   if (dup) {
-    // Sequential replay of Floyd's insertions by wave 0.
-    if (threadIdx.x < 64) {
-      const int lane = threadIdx.x;
-      uint32_t slot[DRAW_SLOTS];
+    // Floyd's insertion it (j = m - s + it, r = r_it <= j) keeps r unless an
+    // earlier insertion already holds r, and then takes j. Every earlier
+    // value is below j, so j itself never repeats one, and whether r_it is a
+    // repeat depends only on the decisions of insertions before it. Jacobi
+    // rounds over all insertions at once therefore reach the sequential
+    // decisions exactly: after round k the first k are final, and the rounds
+    // stop at the first one that changes nothing (at most s + 1 rounds;
+    // about one more than the longest chain of repeats in practice).
+    __shared__ uint32_t rv[DRAW_SMAX];
+    __shared__ uint8_t took_j[DRAW_SMAX];
+    __shared__ int changed;
+    for (int i = threadIdx.x; i < s; i += blockDim.x) {
+      rv[i] = floyd_r(key1, (uint64_t)(m - s + i));
+      took_j[i] = 0;
+    }
+    __syncthreads();
+    for (int round = 0; round <= s; ++round) {
+      if (threadIdx.x == 0) changed = 0;
+      // a thread has at most two insertions: the launches give s <= 2 blockDim
+      uint8_t next[2] = {0, 0};
 #pragma unroll
-      for (int q = 0; q < DRAW_SLOTS; ++q) slot[q] = 0xFFFFFFFFu;
-      for (int it = 0; it < s; ++it) {
-        const uint32_t j = (uint32_t)(m - s + it);
-        const uint32_t r = floyd_r(key1, j);
-        bool hit = false;
-#pragma unroll
-        for (int q = 0; q < DRAW_SLOTS; ++q) hit |= (slot[q] == r);
-        const bool found = __any(hit);
-        const uint32_t v = found ? j : r;
-        if (lane == (it & 63)) {
-          const int qq = it >> 6;
-#pragma unroll
-          for (int q = 0; q < DRAW_SLOTS; ++q)
-            if (q == qq) slot[q] = v;
+      for (int u = 0; u < 2; ++u) {
+        const int i = threadIdx.x + u * (int)blockDim.x;
+        if (i < s) {
+          const uint32_t r = rv[i];
+          bool rep = false;
+#pragma unroll 8
+          for (int k = 0; k < i; ++k) {
+            const uint32_t vk = took_j[k] ? (uint32_t)(m - s + k) : rv[k];
+            rep |= (vk == r);
+          }
+          next[u] = rep ? 1 : 0;
         }
       }
+      __syncthreads();
 #pragma unroll
-      for (int q = 0; q < DRAW_SLOTS; ++q) {
-        const int idx = lane + 64 * q;
-        if (idx < P) keys[idx] = (idx < s) ? slot[q] : 0xFFFFFFFFu;
+      for (int u = 0; u < 2; ++u) {
+        const int i = threadIdx.x + u * (int)blockDim.x;
+        if (i < s && next[u] != took_j[i]) {
+          took_j[i] = next[u];
+          changed = 1;
+        }
       }
+      __syncthreads();
+      if (!changed) break;
+      __syncthreads();
     }
+    for (int i = threadIdx.x; i < P; i += blockDim.x)
+      keys[i] = (i < s) ? (took_j[i] ? (uint32_t)(m - s + i) : rv[i]) : 0xFFFFFFFFu;
     __syncthreads();
     bitonic_sort(keys, P);
   }
