@@ -31,7 +31,7 @@
  *     after synchronizing the stream;
  *   - results are deterministic: the same inputs, seed and device give
  *     bitwise-identical outputs (no floating-point atomics).
- * Limits of this build: 1 <= n <= 128, n <= s <= m, m < 2^28, and the
+ * Limits of this library: 1 <= n <= 128, n <= s <= m, m < 2^28, and the
  * sketch must fit the one-workgroup Householder QR: s <= 2048 for n <= 16,
  * s <= 1024 for n <= 32, s <= 512 for n <= 64, s <= 256 for n <= 128
  * (the default s = 2n always fits).
@@ -82,7 +82,7 @@ enum mrcqr_status {
                                      kappa(Rc) exceeds the posterior bound: the
                                      sketch precision was too low for A (Section
                                      "Adaptive Precision Selection", rerun rule)  */
-  MRCQR_ERR_UNSUPPORTED = 8       /* shape outside this build's limits (synchronous) */
+  MRCQR_ERR_UNSUPPORTED = 8       /* shape outside this library's limits (synchronous) */
 };
 
 /* Per-call outcome, written by the device at the end of the call. */

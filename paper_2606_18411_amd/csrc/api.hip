@@ -592,7 +592,7 @@ const char* mrcqr_status_string(int status) {
     case MRCQR_ERR_WORKSPACE: return "workspace missing or too small";
     case MRCQR_ERR_DEVICE: return "HIP runtime error";
     case MRCQR_WARN_POSTERIOR: return "posterior check: kappa(Rc) above bound, sketch precision too low";
-    case MRCQR_ERR_UNSUPPORTED: return "shape not supported by this build";
+    case MRCQR_ERR_UNSUPPORTED: return "shape not supported by this library";
     default: return "unknown status";
   }
 }

@@ -53,7 +53,7 @@ def test_argument_errors_are_synchronous(lib):
              ((100, 10, 100, 7, 0, 100, 10), 1),    # bad precision
              ((100, 0, 100, 3, 0, 100, 1), 1),      # n = 0
              ((100, 10, 100, 3, 0, 100, 9), 1),     # ldr < n
-             ((1000, 200, 1000, 3, 0, 1000, 200), 8)]  # n above this build's limit
+             ((1000, 200, 1000, 3, 0, 1000, 200), 8)]  # n above this library's limit
     for (m, n, lda, prec, s, ldq, ldr), want in cases:
         if want is None:
             continue
@@ -94,7 +94,7 @@ def test_batch_and_regime_argument_errors(lib):
     p = vp()
     cases = [((), (), 1),                         # empty batch
              ((100, 64), (10, 40), 1),            # member 1: s = 2n > m
-             ((1000, 1000), (10, 200), 8),        # member 1: n above this build's limit
+             ((1000, 1000), (10, 200), 8),        # member 1: n above this library's limit
              ((1000,), (0,), 1),                  # n = 0
              ((1 << 28,), (4,), 8)]               # m beyond the exact-phase row limit
     for ms, ns, want in cases:
