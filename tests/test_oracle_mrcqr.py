@@ -178,3 +178,27 @@ def test_ice_estimate_tracks_kappa_of_sketch_factor(mats):
         _, _, _, Rs = M.stage1(mats[kappa], P.FP64, 16, 2 * n)
         k = CE.kappa_est(Rs)
         assert kappa / 20 < k <= kappa * 1.01
+
+
+@pytest.mark.parametrize("start", [P.FP32, P.FP64])
+def test_auto_started_higher_never_goes_below_its_start(mats, start):
+    """Repeated calls start AUTO from the precision the previous call
+    accepted: started at p on an easy matrix, it stays at p with no
+    escalation and reproduces the factorization forced to p exactly (the
+    AUTO branch against the fixed-precision branch)."""
+    A = mats[1e2]
+    r = M.factor(A, M.AUTO, seed=13, start=start)
+    f = M.factor(A, start, seed=13)
+    assert (r.status, r.precision_used, r.escalations) == (M.STATUS_OK, start, 0)
+    assert np.array_equal(r.Q, f.Q) and np.array_equal(r.R, f.R)
+
+
+def test_auto_escalation_from_a_carried_start_matches_a_fresh_one(mats):
+    """Started at FP16 on a kappa = 1e8 matrix AUTO escalates to FP32; started
+    at FP32 it lands there directly with the same result."""
+    A = mats[1e8]
+    a = M.factor(A, M.AUTO, seed=13)
+    b = M.factor(A, M.AUTO, seed=13, start=P.FP32)
+    assert a.precision_used == b.precision_used == P.FP32
+    assert a.escalations == 1 and b.escalations == 0
+    assert np.array_equal(a.Q, b.Q) and np.array_equal(a.R, b.R)
