@@ -89,3 +89,40 @@ def kappa_est(R: np.ndarray) -> float:
     if not np.isfinite(smin) or not np.isfinite(smax) or smin == 0.0:
         return float("inf")
     return smax / smin
+
+
+# ---- posterior estimate of kappa_2(Rc) -------------------------------------
+# The posterior check of the adaptive policy (Section "Adaptive Precision
+# Selection": a result whose orthogonality is lost is detected and the
+# factorization rerun one precision higher) needs kappa_2(Rc) = kappa_2(B)
+# without forming Q^T Q. ICE alone can underestimate it several-fold on the
+# well-conditioned factors met there, so the estimate also runs a few steps
+# of the power method (Golub and Van Loan, Section 8.2) on Rc^T Rc and on
+# X^T X with X = Rc^{-1} (which the factorization forms anyway), each started
+# from the normalized all-ones vector. Every quantity is a lower bound of
+# its exact counterpart, and so is their maximum.
+POWER_STEPS = 12
+
+
+def power_norm(M: np.ndarray, steps: int = POWER_STEPS) -> float:
+    """||M x|| after `steps` normalized applications of M^T M to x0 =
+    ones/sqrt(n): a lower bound on sigma_max(M)."""
+    M = np.asarray(M, dtype=np.float64)
+    n = M.shape[1]
+    x = np.full(n, 1.0 / np.sqrt(n))
+    for _ in range(steps):
+        z = M.T @ (M @ x)
+        nz = float(np.linalg.norm(z))
+        if not np.isfinite(nz) or nz == 0.0:
+            return nz
+        x = z / nz
+    return float(np.linalg.norm(M @ x))
+
+
+def kappa_posterior(Rc: np.ndarray, X: np.ndarray) -> float:
+    """max(ICE(Rc), power_norm(Rc) * power_norm(X)), X = Rc^{-1}."""
+    k_ice = kappa_est(Rc)
+    k_pow = power_norm(Rc) * power_norm(X)
+    if not np.isfinite(k_ice) or not np.isfinite(k_pow):
+        return float("inf")
+    return max(k_ice, k_pow)

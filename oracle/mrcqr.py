@@ -13,9 +13,11 @@ in Section "Adaptive Precision Selection" but no estimator): start at
 ICE; if it reaches the regime bound of the current precision (1e4 for half,
 1e8 for single) or Rs is not finite / has a zero pivot, redo Stage 1 one
 level higher. After Stage 2 a posterior check on kappa(R2) = kappa(A1)
-(Cholesky-QR loses orthogonality like kappa(A1)^2 u) triggers one more
-rerun at the next level when it exceeds TAU_POSTERIOR or the Cholesky
-breaks down: the paper's self-correcting rerun.
+(Cholesky-QR loses orthogonality like kappa(A1)^2 u; the estimate is
+condest.kappa_posterior, ICE combined with a few power steps on R2 and
+R2^{-1}) triggers a rerun at the next level when it exceeds TAU_POSTERIOR
+or the Cholesky breaks down, as many times as there is a next level: the
+paper's self-correcting rerun.
 """
 from __future__ import annotations
 
@@ -27,7 +29,7 @@ from . import rng, sketch as SK, householder as HH, cholqr as CQ, condest as CE
 from . import precision as P
 
 AUTO = 0
-TAU = {P.FP16: 1e4, P.BF16: 1e2, P.FP32: 1e8, P.FP64: float("inf")}
+TAU = {P.FP16: 1e4, P.FP32: 1e8, P.FP64: float("inf")}
 TAU_POSTERIOR = 20.0
 LADDER = [P.FP16, P.FP32, P.FP64]
 
@@ -68,6 +70,11 @@ def stage2(A: np.ndarray, Rs: np.ndarray):
     return B, G, Rc, Q
 
 
+def posterior_kappa(Rc: np.ndarray) -> float:
+    """Estimate of kappa_2(Rc) for the posterior check (see condest)."""
+    return CE.kappa_posterior(Rc, CQ.upper_inverse(Rc))
+
+
 def _rs_ok(Rs: np.ndarray) -> bool:
     d = np.diag(Rs)
     return bool(np.all(np.isfinite(Rs)) and np.all(d > 0))
@@ -88,7 +95,7 @@ def factor(A: np.ndarray, precision: int, seed: int, s: int | None = None,
             B, G, Rc, Q = stage2(A, Rs)
         except CQ.CholeskyBreakdown as e:
             return Result(None, None, STATUS_CHOL_BREAKDOWN, precision, 0, krs, float("nan"), e.index, inter)
-        krc = CE.kappa_est(Rc)
+        krc = posterior_kappa(Rc)
         if keep:
             inter.update({"B": B, "G": G, "Rc": Rc})
         st = STATUS_OK if krc <= TAU_POSTERIOR else STATUS_POSTERIOR_WARN
@@ -96,7 +103,6 @@ def factor(A: np.ndarray, precision: int, seed: int, s: int | None = None,
 
     level = LADDER.index(start)
     escalations = 0
-    posterior_used = False
     while True:
         prec = LADDER[level]
         S, d, Y, Rs = stage1(A, prec, seed, s)
@@ -110,12 +116,11 @@ def factor(A: np.ndarray, precision: int, seed: int, s: int | None = None,
             return Result(None, None, STATUS_SKETCH_SINGULAR, prec, escalations, krs, float("nan"))
         try:
             B, G, Rc, Q = stage2(A, Rs)
-            krc = CE.kappa_est(Rc)
+            krc = posterior_kappa(Rc)
             fail = -1
         except CQ.CholeskyBreakdown as e:
             krc, fail = float("inf"), e.index
-        if krc > TAU_POSTERIOR and level + 1 < len(LADDER) and not posterior_used:
-            posterior_used = True
+        if krc > TAU_POSTERIOR and level + 1 < len(LADDER):
             level += 1
             escalations += 1
             continue

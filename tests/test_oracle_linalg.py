@@ -232,3 +232,24 @@ def test_ice_step_eigenpair_definition():
             v = np.array([s, c])
             assert abs(np.hypot(s, c) - 1) < 1e-15
             assert np.linalg.norm(M @ v - lam * v) <= 1e-14 * max(1.0, np.abs(M).max())
+
+
+def test_power_norm_exact_on_diagonal_and_rank_one():
+    # diagonal: the iteration converges to the largest entry (ratio of the
+    # two largest (1/3)^24 after 12 steps); rank one u v^T: exact after one step
+    D = np.diag([1.0, 3.0, 0.5, 0.25])
+    assert abs(CE.power_norm(D) - 3.0) < 1e-9
+    u, v = np.array([1.0, -2.0, 0.5]), np.array([0.3, 0.4, 1.2])
+    assert abs(CE.power_norm(np.outer(u, v)) - np.linalg.norm(u) * np.linalg.norm(v)) < 1e-12
+
+
+@pytest.mark.parametrize("kappa", [2.0, 10.0, 1e3, 1e8])
+def test_posterior_estimate_is_a_tight_lower_bound(kappa):
+    for seed in range(6):
+        R = W.upper_triangular(24, kappa, 40 + seed)
+        X = np.linalg.inv(R)
+        sv = np.linalg.svd(R, compute_uv=False)
+        k2 = sv[0] / sv[-1]
+        est = CE.kappa_posterior(R, X)
+        assert CE.kappa_est(R) <= est <= k2 * (1 + 1e-10)
+        assert est >= 0.6 * k2

@@ -202,3 +202,75 @@ def test_auto_escalation_from_a_carried_start_matches_a_fresh_one(mats):
     assert a.precision_used == b.precision_used == P.FP32
     assert a.escalations == 1 and b.escalations == 0
     assert np.array_equal(a.Q, b.Q) and np.array_equal(a.R, b.R)
+
+
+def _lapack_r(Y, dtype):
+    import scipy.linalg
+    R = scipy.linalg.qr(np.asarray(Y, dtype=dtype), mode="r")[0][: Y.shape[1]]
+    d = np.sign(np.diag(R))
+    d[d == 0] = 1
+    return np.triu(R * d[:, None]).astype(np.float64)
+
+
+@pytest.mark.parametrize("prec,kappa", [(P.FP16, 1e2), (P.FP16, 1e4), (P.BF16, 1e2), (P.FP32, 1e4),
+                                        (P.FP32, 1e8)])
+def test_sketch_qr_runs_in_single_precision(mats, prec, kappa):
+    """Section "Algorithm Description": the sketch QR of a half, bfloat16 or
+    single sketch is a single-precision QR (no half QR exists). Rs is then a
+    float32 value before its promotion, and agrees with float32 LAPACK
+    (sgeqrf, through scipy) within c n u32 kappa."""
+    _, _, Y, Rs = M.stage1(mats[kappa], prec, 17, 2 * n)
+    assert np.array_equal(Rs.astype(np.float32).astype(np.float64), Rs)
+    Rl = _lapack_r(Y, np.float32)
+    k = np.linalg.cond(Y)
+    assert MT.rel_diff(Rs, Rl) <= 20 * n * 2.0 ** -24 * k
+
+
+def test_fp64_sketch_qr_runs_in_double_precision(mats):
+    _, _, Y, Rs = M.stage1(mats[1e8], P.FP64, 17, 2 * n)
+    assert not np.array_equal(Rs.astype(np.float32).astype(np.float64), Rs)
+    assert MT.rel_diff(Rs, _lapack_r(Y, np.float64)) <= 20 * n * 2.0 ** -53 * 1e8
+
+
+def test_posterior_bound_keeps_orthogonality_within_target():
+    """The posterior bound tau_c on kappa(Rc) = kappa(A Rs^-1): Cholesky-QR
+    loses orthogonality like kappa^2 u, so tau_c^2 u must stay below the
+    paper's 1e-13 target."""
+    assert M.TAU_POSTERIOR ** 2 * 2.0 ** -53 <= CLAIMS["target_orthogonality"]
+
+
+@pytest.mark.parametrize("s,seed", [(17, 0), (18, 26)])
+def test_posterior_check_reruns_up_the_ladder(s, seed):
+    """A sketch with barely more rows than columns leaves kappa(Rc) between
+    tau_c = 20 and 30 at every precision (the draw, not the precision, is
+    the cause): AUTO reruns at FP32, then at FP64, and reports the posterior
+    warning (Section "Adaptive Precision Selection": rerun at the next
+    higher level)."""
+    A = W.test_matrix(2048, 16, 1e2, 3)
+    r = M.factor(A, M.AUTO, seed, s=s)
+    assert 20.0 < r.kappa_rc < 30.0
+    assert (r.status, r.precision_used, r.escalations) == (M.STATUS_POSTERIOR_WARN, P.FP64, 2)
+    f = M.factor(A, P.FP16, seed, s=s)
+    assert f.status == M.STATUS_POSTERIOR_WARN and 20.0 < f.kappa_rc < 30.0
+
+
+def test_accepted_results_meet_the_target_and_estimate_is_tight():
+    """Every result the policy accepts (status 0) meets ||I - Q^T Q|| <= 1e-13,
+    including sketches barely taller than n where kappa(Rc) is large, and the
+    posterior estimate is within a factor 0.6 of kappa_2(Rc)."""
+    m_, n_ = 2048, 16
+    accepted = 0
+    for kappa in [1e2, 1e4, 1e8]:
+        A = W.test_matrix(m_, n_, kappa, 3)
+        for s in [17, 20, 32]:
+            for prec in [P.FP16, P.FP32, P.FP64]:
+                for seed in range(6):
+                    r = M.factor(A, prec, seed, s=s, keep=True)
+                    if "Rc" not in r.intermediates:
+                        continue
+                    sv = np.linalg.svd(r.intermediates["Rc"], compute_uv=False)
+                    assert r.kappa_rc >= 0.6 * sv[0] / sv[-1]
+                    if r.status == M.STATUS_OK:
+                        accepted += 1
+                        assert MT.orthogonality(r.Q) <= CLAIMS["target_orthogonality"]
+    assert accepted > 50

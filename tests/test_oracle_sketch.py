@@ -82,3 +82,33 @@ def test_low_precision_sketch_uses_rounded_inputs():
     Y1 = SK.sketch(A, S, d, P.FP16)
     Y2 = SK.sketch(A * (1 + 2.0 ** -20), S, d, P.FP16)
     assert np.array_equal(Y1, Y2)
+
+
+def _coefficient_cases():
+    import os
+    from conftest import GOLDEN
+    out = {}
+    for line in open(os.path.join(GOLDEN, "sketch_coefficients.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        fmt, i, j, y = line.split()
+        out.setdefault(fmt, {})[(int(i), int(j))] = float.fromhex(y)
+    return out
+
+
+@pytest.mark.parametrize("fmt,prec", [("fp16", P.FP16), ("bf16", P.BF16), ("fp32", P.FP32)])
+def test_sketch_of_unit_vectors_matches_hand_derived_values(fmt, prec):
+    """Algorithm 2, Stage 1 in precision p: the cosine coefficients are
+    rounded to p (unit-vector columns expose fl_p(c) directly) and the
+    float32-accumulated Y is a float32 value (column 8's exact sum needs 31
+    bits). Values: tests/golden/sketch_coefficients.txt, derived from 60-digit
+    cosines and the formats' spacing, not from this oracle."""
+    want = _coefficient_cases()[fmt]
+    m = 8
+    A = np.zeros((m, 9))
+    A[np.arange(m), np.arange(m)] = 1.0
+    A[0, 8], A[1, 8] = 1.0, 2.0 ** -20
+    d = np.array([1, 1, 1, -1, 1, 1, -1, 1], dtype=np.float64)
+    Y = SK.sketch(A, np.array([1, 2]), d, prec)
+    for (i, j), y in want.items():
+        assert Y[i, j] == y, (fmt, i, j, Y[i, j].hex(), y.hex())
