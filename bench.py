@@ -172,21 +172,24 @@ def main() -> int:
 
     ms16 = run_path("fp16", args.steps, args.warmup)
     ms64 = run_path("fp64", args.steps, args.warmup)
+    # the product's default policy: AUTO decides the precision on the device
+    ms_auto = run_path("auto", args.steps, args.warmup)
 
     # accuracy of both paths (untimed)
     from oracle import metrics as MT
     acc = {}
-    for prec in ("fp16", "fp64"):
+    for prec in ("fp16", "fp64", "auto"):
         plan.execute(A, Q, R, prec, seed=7)
         torch.cuda.synchronize()
         info = plan.last_info()
         Qh, Rh = Q.cpu().numpy(), R.cpu().numpy()
         acc[prec] = {"orthogonality": MT.orthogonality(Qh), "residual": MT.residual(A_h, Qh, Rh, 1.0),
-                     "status": info.status, "kappa_rs_est": info.kappa_rs_est, "kappa_rc_est": info.kappa_rc_est}
+                     "status": info.status, "precision_used": info.precision, "escalations": info.escalations,
+                     "kappa_rs_est": info.kappa_rs_est, "kappa_rc_est": info.kappa_rc_est}
         log(f"{prec} accuracy: {acc[prec]}")
     del Qh
 
-    # dominant kernel: the float64 triangular solve X = A R^{-1} (launched twice per QR).
+    # dominant kernel: the float64 triangular solve B = A Rs^{-1} (once per QR).
     Rs = torch.from_numpy(np.ascontiguousarray(np.triu(R.cpu().numpy()).T)).cuda().t()
     X = M.empty_colmajor(m, n)
     tws = torch.empty(int(M.lib().mrcqr_trsm_workspace_bytes(n)), dtype=torch.uint8, device="cuda")
@@ -239,6 +242,8 @@ def main() -> int:
         "config": {"workload": f"MRCQR thin QR, m={m}, n={n}, s={s}, kappa={kappa:g}, A=U diag(sigma) V^T",
                    "m": m, "n": n, "s": s, "kappa": kappa, "sketch_precision": "fp16"},
         "fp64_sketch_ms_per_qr": round(ms64, 5),
+        "auto_ms_per_qr": round(ms_auto, 5),
+        "auto_precision_used": acc["auto"]["precision_used"],
         "fp16_over_fp64_speedup": round(ms64 / ms16, 4),
         "gflops_at_2mn2": {"fp16": round(flop_2mn2 / (ms16 * 1e-3) / 1e9, 2),
                            "fp64": round(flop_2mn2 / (ms64 * 1e-3) / 1e9, 2)},

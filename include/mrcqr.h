@@ -23,10 +23,13 @@
  *     torch-allocated memory on the current device); the library never
  *     frees or retains caller memory past the call;
  *   - `stream` is a hipStream_t (NULL = the legacy default stream); all
- *     work is enqueued asynchronously on it; nothing synchronizes;
+ *     work is enqueued asynchronously on it; no entry point waits for the
+ *     device, except mrcqr_factor_batched (blocking argument copy) and
+ *     mrcqr_release_cache;
  *   - argument errors are returned synchronously (MRCQR_ERR_ARG /
  *     MRCQR_ERR_UNSUPPORTED) before anything is launched; numeric outcomes
- *     (Cholesky breakdown, singular sketch, posterior warning) are written
+ *     (non-finite sketch, Cholesky breakdown, singular sketch, posterior
+ *     warning) are written
  *     asynchronously to a device-resident mrcqr_info that the caller reads
  *     after synchronizing the stream;
  *   - results are deterministic: the same inputs, seed and device give
@@ -50,7 +53,8 @@ extern "C" {
  * Selection": half for kappa < 1e4, single below 1e8, double otherwise).
  * BF16 is an extra option (8-bit exponent, 8-bit significand).
  * AUTO starts at FP16 and escalates per call from an on-device condition
- * estimate of Rs (see mrcqr_factor).
+ * estimate of Rs, and reruns one precision higher when the posterior check
+ * fails (see mrcqr_factor).
  * AUTO_CARRY is AUTO for a sequence of similar matrices (block Arnoldi,
  * power iterations: Section "Adaptive Precision Selection", repeated
  * calls): a call starts from the precision that the previous AUTO_CARRY
@@ -58,8 +62,10 @@ extern "C" {
  * from there as AUTO does. The record lives in the workspace on the device,
  * so it also carries across the replays of a captured graph; it never moves
  * down (mrcqr_regime_reset forgets it). A workspace without a record (all
- * zero bytes, as mrcqr_factor's own cached workspaces start) starts from
- * FP16. Calls sharing one workspace share its record. */
+ * zero bytes) starts from FP16. Calls sharing one workspace share its
+ * record, so AUTO_CARRY needs a workspace owned by the caller: the plan and
+ * batch-plan APIs accept it, mrcqr_factor and mrcqr_factor_batched (whose
+ * workspaces are shared per shape) return MRCQR_ERR_ARG. */
 enum mrcqr_precision {
   MRCQR_PREC_AUTO = 0,
   MRCQR_PREC_FP64 = 1,
@@ -72,7 +78,11 @@ enum mrcqr_precision {
 enum mrcqr_status {
   MRCQR_OK = 0,
   MRCQR_ERR_ARG = 1,              /* invalid argument (synchronous)               */
-  MRCQR_ERR_NONFINITE = 2,        /* non-finite value met in the sketch           */
+  MRCQR_ERR_NONFINITE = 2,        /* the sketch Y holds inf or NaN: A has a
+                                     non-finite entry, or entries beyond the
+                                     range of the sketch precision (AUTO then
+                                     escalates; reported at FP64 or a forced
+                                     precision)                                 */
   MRCQR_ERR_CHOL_BREAKDOWN = 3,   /* Gram matrix not numerically SPD (Algorithm 1
                                      breakdown); chol_fail_index = first pivot   */
   MRCQR_ERR_SKETCH_SINGULAR = 4,  /* Rs has a zero or non-finite diagonal entry   */
@@ -94,7 +104,9 @@ typedef struct mrcqr_info {
   double kappa_rs_est;     /* ICE estimate of kappa_2(Rs) (a lower bound); only
                               AUTO computes it: NaN for a forced precision,
                               +inf when Rs was singular                      */
-  double kappa_rc_est;     /* ICE estimate of kappa_2(Rc) = kappa_2(B)         */
+  double kappa_rc_est;     /* posterior estimate of kappa_2(Rc) = kappa_2(B):
+                              the larger of ICE and 12 power steps on Rc and
+                              Rc^{-1} (both lower bounds); +inf on breakdown */
 } mrcqr_info;
 
 typedef struct mrcqr_plan mrcqr_plan;
@@ -108,10 +120,21 @@ typedef struct mrcqr_plan mrcqr_plan;
  * seed: selects D and S (counter-based SplitMix64 draw, Floyd sampling).
  * info_dev: device pointer to one mrcqr_info (may be NULL).
  * The workspace comes from a per-device cache keyed by (m, n, s), created
- * on first use with hipMalloc; use the plan API to supply it yourself.
+ * on first use with hipMalloc (no memset, no wait for the device) and kept
+ * until mrcqr_release_cache; use the plan API to supply it yourself. Calls
+ * of one shape are serialized on the device through an event of the cached
+ * workspace (the stream of a call waits for the previous call of that
+ * shape, whatever its stream or host thread), so they never race. Under
+ * stream capture the event edges are left out: a captured call shares the
+ * workspace with every other call of its shape, and replays must not
+ * overlap them (the plan API gives a capture its own workspace).
  * AUTO: Stage 1 runs in FP16; if the ICE estimate of kappa(Rs) is >= 1e4
- * it is redone in FP32, and if that estimate is >= 1e8, in FP64. The
- * decision is taken on the device (no host round trip).
+ * it is redone in FP32, and if that estimate is >= 1e8, in FP64. After
+ * Stage 2 the posterior check (estimate of kappa(Rc) above 20, or a
+ * Cholesky breakdown) reruns the factorization one precision higher, up to
+ * FP64 (Section "Adaptive Precision Selection", rerun rule). All decisions
+ * are taken on the device (no host round trip). AUTO_CARRY is rejected
+ * (MRCQR_ERR_ARG): use the plan API.
  * Returns MRCQR_OK when the work was enqueued.
  * ------------------------------------------------------------------- */
 int mrcqr_factor(const double* A, int64_t m, int64_t n, int64_t lda,
@@ -119,7 +142,14 @@ int mrcqr_factor(const double* A, int64_t m, int64_t n, int64_t lda,
                  double* Q, int64_t ldq, double* R, int64_t ldr,
                  void* stream, mrcqr_info* info_dev);
 
-/* Plan API: a plan fixes (m, n, s); execute allocates nothing. */
+/* Wait for and free the workspaces cached by mrcqr_factor and
+ * mrcqr_factor_batched on every device. No call of those may run
+ * concurrently with it. Returns MRCQR_ERR_DEVICE if a HIP call failed. */
+int mrcqr_release_cache(void);
+
+/* Plan API: a plan fixes (m, n, s); execute allocates nothing. Calls that
+ * share a workspace must not overlap on the device (one stream, or events
+ * between streams). */
 int mrcqr_plan_create(int64_t m, int64_t n, int64_t s, mrcqr_plan** out);
 size_t mrcqr_plan_workspace_bytes(const mrcqr_plan* plan);
 int mrcqr_execute(const mrcqr_plan* plan, void* workspace, size_t workspace_bytes,
@@ -175,11 +205,12 @@ int mrcqr_batch_execute(const mrcqr_batch_plan* plan, void* workspace, size_t wo
 
 /* The same with HOST per-member arrays (the matrices are device memory),
  * checked synchronously like mrcqr_factor. A batch plan, its workspace
- * (zeroed when created) and the argument arrays are cached per device and
- * shape list; the arrays are copied to the device with a blocking copy, after
- * the previous call with the same shape list has finished reading them.
- * Not for graph capture (use mrcqr_batch_execute). infos_dev: device array
- * of `batch` infos (or NULL). */
+ * and the argument arrays are cached per device and shape list (freed by
+ * mrcqr_release_cache); the arrays are copied to the device with a blocking
+ * copy, after the previous call with the same shape list has finished
+ * reading them. AUTO_CARRY members are rejected (MRCQR_ERR_ARG). Not for
+ * graph capture (use mrcqr_batch_execute). infos_dev: device array of
+ * `batch` infos (or NULL). */
 int mrcqr_factor_batched(int32_t batch, const double* const* A, const int64_t* m,
                          const int64_t* n, const int64_t* lda, const int32_t* precision,
                          const uint64_t* seeds, double* const* Q, const int64_t* ldq,
@@ -254,12 +285,21 @@ int mrcqr_tri_inverse(const double* R, int64_t n, int64_t ldr, double* X, int64_
 int mrcqr_form_q(const double* B, int64_t m, int64_t n, int64_t ldb, const double* X, int64_t ldx,
                  double* Q, int64_t ldq, void* stream);
 
-/* Stage 3: R = R2 R1 for upper-triangular n x n factors. */
+/* Stage 3: R = R2 R1 for upper-triangular n x n factors (n <= 128). */
 int mrcqr_trmm(const double* R2, int64_t ld2, const double* R1, int64_t ld1,
                int64_t n, double* R, int64_t ldr, void* stream);
 
 /* ICE condition estimate of an upper-triangular n x n matrix. */
 int mrcqr_condest(const double* R, int64_t n, int64_t ldr, double* kappa_dev, void* stream);
+
+/* Power-step part of the posterior estimate (Section "Adaptive Precision
+ * Selection", rerun rule): kappa_dev receives sigma_max(R) sigma_max(X)
+ * estimated by 12 power steps on R^T R and X^T X from the normalized
+ * all-ones vector, for an upper-triangular n x n R (n <= 128) and X =
+ * R^{-1} (from mrcqr_tri_inverse), both with leading dimension ld. A lower
+ * bound on kappa_2(R); +inf if a value is not finite. */
+int mrcqr_posterior_kappa(const double* R, const double* X, int64_t n, int64_t ld, double* kappa_dev,
+                          void* stream);
 
 const char* mrcqr_status_string(int status);
 /* Library version as major * 10000 + minor * 100 + patch. */

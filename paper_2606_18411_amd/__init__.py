@@ -68,6 +68,8 @@ def lib() -> ctypes.CDLL:
             "mrcqr_tri_inverse": (i32, [vp, i64, i64, vp, i64, vp]),
             "mrcqr_form_q": (i32, [vp, i64, i64, i64, vp, i64, vp, i64, vp]),
             "mrcqr_condest": (i32, [vp, i64, i64, vp, vp]),
+            "mrcqr_posterior_kappa": (i32, [vp, vp, i64, i64, vp, vp]),
+            "mrcqr_release_cache": (i32, []),
             "mrcqr_regime_reset": (i32, [vp, vp, sz, vp]),
             "mrcqr_batch_plan_create": (i32, [i32, vp, vp, ctypes.POINTER(vp)]),
             "mrcqr_batch_plan_workspace_bytes": (sz, [vp]),
@@ -113,14 +115,37 @@ def empty_colmajor(m: int, n: int, device="cuda", dtype=torch.float64) -> torch.
 
 
 def _ld(x: torch.Tensor) -> int:
-    if x.dim() != 2 or x.stride(0) != 1:
+    if x.dim() != 2 or (x.shape[0] > 1 and x.stride(0) != 1):
         raise ValueError("matrices must be column-major (stride(0) == 1)")
     return max(x.stride(1), x.shape[0], 1)
 
 
-def _f64_cuda(x: torch.Tensor, name: str) -> None:
-    if not (x.is_cuda and x.dtype == torch.float64):
-        raise TypeError(f"{name} must be a float64 CUDA tensor")
+def _mat(x, rows: int, cols: int, name: str) -> None:
+    """Check before any launch that x is a column-major float64 matrix of
+    shape (rows, cols): the library can only check leading dimensions, so a
+    wrong shape or dtype would turn into out-of-bounds device accesses."""
+    if not isinstance(x, torch.Tensor) or x.dim() != 2:
+        raise ValueError(f"{name} must be a 2-D tensor")
+    if tuple(x.shape) != (rows, cols):
+        raise ValueError(f"{name} has shape {tuple(x.shape)}, expected ({rows}, {cols})")
+    if x.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64, got {x.dtype}")
+    # a single row or column has no layout to check in that dimension
+    if (rows > 1 and x.stride(0) != 1) or (cols > 1 and x.stride(1) < rows):
+        raise ValueError(f"{name} must be column-major (stride (1, ld), ld >= {rows})")
+
+
+def _same_cuda_device(named, device=None) -> None:
+    """Every tensor of `named` ((name, tensor) pairs) is a CUDA tensor on one
+    device (`device` when given). Checked after the shapes, last before the
+    library is called."""
+    for name, x in named:
+        if not x.is_cuda:
+            raise TypeError(f"{name} must be a CUDA tensor")
+        if device is None:
+            device = x.device
+        elif x.device != torch.device(device):
+            raise ValueError(f"{name} is on {x.device}, expected {device}")
 
 
 @dataclass
@@ -157,8 +182,15 @@ def factor(A: torch.Tensor, precision="fp16", seed: int = 0, s: int | None = Non
            Q: torch.Tensor | None = None, R: torch.Tensor | None = None, stream=None,
            sync: bool = True):
     """Thin QR A = Q R by MRCQR. Returns (Q, R, Info) (Info None if sync=False)."""
-    _f64_cuda(A, "A")
+    if not isinstance(A, torch.Tensor) or A.dim() != 2:
+        raise ValueError("A must be a 2-D tensor")
     m, n = A.shape
+    _mat(A, m, n, "A")
+    if Q is not None:
+        _mat(Q, m, n, "Q")
+    if R is not None:
+        _mat(R, n, n, "R")
+    _same_cuda_device([("A", A)] + ([("Q", Q)] if Q is not None else []) + ([("R", R)] if R is not None else []))
     if Q is None:
         Q = empty_colmajor(m, n, A.device)
     if R is None:
@@ -187,6 +219,10 @@ class Plan:
         self.info = torch.empty(INFO_BYTES, dtype=torch.uint8, device=device)
 
     def execute(self, A, Q, R, precision="fp16", seed: int = 0, stream=None):
+        _mat(A, self.m, self.n, "A")
+        _mat(Q, self.m, self.n, "Q")
+        _mat(R, self.n, self.n, "R")
+        _same_cuda_device([("A", A), ("Q", Q), ("R", R)], self.workspace.device)
         _check(lib().mrcqr_execute(self._p, self.workspace.data_ptr(), self.workspace_bytes, A.data_ptr(), _ld(A),
                                    _prec(precision), seed & (2 ** 64 - 1), Q.data_ptr(), _ld(Q), R.data_ptr(),
                                    _ld(R), _stream(stream), self.info.data_ptr()), "mrcqr_execute")
@@ -234,8 +270,20 @@ class BatchPlan:
     def bind(self, As, Qs, Rs, precisions, seeds):
         """Per-member arguments as device arrays (kept alive by the plan)."""
         dev = self.device
+        k = len(self.shapes)
+        if not (len(As) == len(Qs) == len(Rs) == k) or len(list(seeds)) != k:
+            raise ValueError(f"expected {k} members in As, Qs, Rs and seeds")
+        named = []
+        for i, ((m, n), a, q, r) in enumerate(zip(self.shapes, As, Qs, Rs)):
+            _mat(a, m, n, f"As[{i}]")
+            _mat(q, m, n, f"Qs[{i}]")
+            _mat(r, n, n, f"Rs[{i}]")
+            named += [(f"As[{i}]", a), (f"Qs[{i}]", q), (f"Rs[{i}]", r)]
+        _same_cuda_device(named, self.workspace.device)
         i64 = lambda vals: torch.tensor(vals, dtype=torch.int64, device=dev)
         precs = precisions if isinstance(precisions, (list, tuple)) else [precisions] * len(As)
+        if len(precs) != k:
+            raise ValueError(f"expected {k} precisions")
         self._args = (
             i64([a.data_ptr() for a in As]), i64([_ld(a) for a in As]),
             torch.tensor([_prec(q) for q in precs], dtype=torch.int32, device=dev),
@@ -247,6 +295,8 @@ class BatchPlan:
 
     def execute(self, stream=None, infos=True):
         a = self._args
+        if a is None:
+            raise RuntimeError("BatchPlan.execute before bind()")
         _check(lib().mrcqr_batch_execute(self._p, self.workspace.data_ptr(), self.workspace_bytes, a[0].data_ptr(),
                                          a[1].data_ptr(), a[2].data_ptr(), a[3].data_ptr(), a[4].data_ptr(),
                                          a[5].data_ptr(), a[6].data_ptr(), a[7].data_ptr(), _stream(stream),
@@ -266,6 +316,11 @@ class BatchPlan:
 def factor_batched(As, precision="auto", seeds=None, stream=None):
     """Factor a list of column-major float64 CUDA matrices; returns (Qs, Rs, infos)."""
     k = len(As)
+    for i, a in enumerate(As):
+        if not isinstance(a, torch.Tensor) or a.dim() != 2:
+            raise ValueError(f"As[{i}] must be a 2-D tensor")
+        _mat(a, a.shape[0], a.shape[1], f"As[{i}]")
+    _same_cuda_device([(f"As[{i}]", a) for i, a in enumerate(As)])
     seeds = list(seeds) if seeds is not None else list(range(k))
     precs = [precision] * k if isinstance(precision, (str, int)) else list(precision)
     Qs = [empty_colmajor(a.shape[0], a.shape[1], a.device) for a in As]
@@ -295,9 +350,14 @@ def draw(seed: int, m: int, s: int, signs: bool = False, device="cuda", stream=N
 
 
 def sketch(A: torch.Tensor, S: torch.Tensor, seed: int, precision="fp16", stream=None) -> torch.Tensor:
-    _f64_cuda(A, "A")
     m, n = A.shape
+    _mat(A, m, n, "A")
+    if not (isinstance(S, torch.Tensor) and S.dim() == 1 and S.dtype == torch.int32):
+        raise TypeError("S must be a 1-D int32 tensor")
     s = S.shape[0]
+    _same_cuda_device([("A", A), ("S", S)])
+    if s < 1 or s > m or int(S.min()) < 0 or int(S.max()) >= m:
+        raise ValueError(f"S must hold 1..m indices in [0, {m})")
     Y = empty_colmajor(s, n, A.device)
     p = _prec(precision)
     wsb = int(lib().mrcqr_sketch_workspace_bytes(m, n, s, p))
@@ -309,6 +369,8 @@ def sketch(A: torch.Tensor, S: torch.Tensor, seed: int, precision="fp16", stream
 
 def sketch_qr(Y: torch.Tensor, precision="fp32", stream=None):
     s, n = Y.shape
+    _mat(Y, s, n, "Y")
+    _same_cuda_device([("Y", Y)])
     Rs = empty_colmajor(n, n, Y.device)
     kappa = torch.empty(1, dtype=torch.float64, device=Y.device)
     _check(lib().mrcqr_sketch_qr(Y.data_ptr(), s, n, _ld(Y), _prec(precision), Rs.data_ptr(), _ld(Rs),
@@ -319,6 +381,11 @@ def sketch_qr(Y: torch.Tensor, precision="fp32", stream=None):
 def trsm(A: torch.Tensor, R: torch.Tensor, X: torch.Tensor | None = None, stream=None,
          workspace: torch.Tensor | None = None) -> torch.Tensor:
     m, n = A.shape
+    _mat(A, m, n, "A")
+    _mat(R, n, n, "R")
+    if X is not None:
+        _mat(X, m, n, "X")
+    _same_cuda_device([("A", A), ("R", R)] + ([("X", X)] if X is not None else []))
     if X is None:
         X = empty_colmajor(m, n, A.device)
     wsb = int(lib().mrcqr_trsm_workspace_bytes(n))
@@ -331,6 +398,8 @@ def trsm(A: torch.Tensor, R: torch.Tensor, X: torch.Tensor | None = None, stream
 
 def gram(B: torch.Tensor, stream=None) -> torch.Tensor:
     m, n = B.shape
+    _mat(B, m, n, "B")
+    _same_cuda_device([("B", B)])
     G = empty_colmajor(n, n, B.device)
     wsb = int(lib().mrcqr_gram_workspace_bytes(m, n))
     ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=B.device)
@@ -341,6 +410,8 @@ def gram(B: torch.Tensor, stream=None) -> torch.Tensor:
 
 def cholesky(G: torch.Tensor, stream=None):
     n = G.shape[0]
+    _mat(G, n, n, "G")
+    _same_cuda_device([("G", G)])
     Rc = empty_colmajor(n, n, G.device)
     fail = torch.empty(1, dtype=torch.int32, device=G.device)
     kappa = torch.empty(1, dtype=torch.float64, device=G.device)
@@ -351,6 +422,9 @@ def cholesky(G: torch.Tensor, stream=None):
 
 def trmm(R2: torch.Tensor, R1: torch.Tensor, stream=None) -> torch.Tensor:
     n = R2.shape[0]
+    _mat(R2, n, n, "R2")
+    _mat(R1, n, n, "R1")
+    _same_cuda_device([("R2", R2), ("R1", R1)])
     R = empty_colmajor(n, n, R2.device)
     _check(lib().mrcqr_trmm(R2.data_ptr(), _ld(R2), R1.data_ptr(), _ld(R1), n, R.data_ptr(), _ld(R),
                             _stream(stream)), "mrcqr_trmm")
@@ -359,6 +433,8 @@ def trmm(R2: torch.Tensor, R1: torch.Tensor, stream=None) -> torch.Tensor:
 
 def tri_inverse(R: torch.Tensor, stream=None) -> torch.Tensor:
     n = R.shape[0]
+    _mat(R, n, n, "R")
+    _same_cuda_device([("R", R)])
     X = empty_colmajor(n, n, R.device)
     _check(lib().mrcqr_tri_inverse(R.data_ptr(), n, _ld(R), X.data_ptr(), _ld(X), _stream(stream)),
            "mrcqr_tri_inverse")
@@ -367,6 +443,11 @@ def tri_inverse(R: torch.Tensor, stream=None) -> torch.Tensor:
 
 def form_q(B: torch.Tensor, X: torch.Tensor, Q: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     m, n = B.shape
+    _mat(B, m, n, "B")
+    _mat(X, n, n, "X")
+    if Q is not None:
+        _mat(Q, m, n, "Q")
+    _same_cuda_device([("B", B), ("X", X)] + ([("Q", Q)] if Q is not None else []))
     if Q is None:
         Q = empty_colmajor(m, n, B.device)
     _check(lib().mrcqr_form_q(B.data_ptr(), m, n, _ld(B), X.data_ptr(), _ld(X), Q.data_ptr(), _ld(Q),
@@ -376,9 +457,31 @@ def form_q(B: torch.Tensor, X: torch.Tensor, Q: torch.Tensor | None = None, stre
 
 def condest(R: torch.Tensor, stream=None) -> torch.Tensor:
     n = R.shape[0]
+    _mat(R, n, n, "R")
+    _same_cuda_device([("R", R)])
     kappa = torch.empty(1, dtype=torch.float64, device=R.device)
     _check(lib().mrcqr_condest(R.data_ptr(), n, _ld(R), kappa.data_ptr(), _stream(stream)), "mrcqr_condest")
     return kappa
+
+
+def posterior_kappa(R: torch.Tensor, X: torch.Tensor, stream=None) -> torch.Tensor:
+    """Power-step estimate sigma_max(R) sigma_max(X) (X = R^{-1}) used by the
+    posterior check; R and X must share one leading dimension."""
+    n = R.shape[0]
+    _mat(R, n, n, "R")
+    _mat(X, n, n, "X")
+    _same_cuda_device([("R", R), ("X", X)])
+    if _ld(R) != _ld(X):
+        raise ValueError("R and X must have the same leading dimension")
+    kappa = torch.empty(1, dtype=torch.float64, device=R.device)
+    _check(lib().mrcqr_posterior_kappa(R.data_ptr(), X.data_ptr(), n, _ld(R), kappa.data_ptr(), _stream(stream)),
+           "mrcqr_posterior_kappa")
+    return kappa
+
+
+def release_cache() -> None:
+    """Wait for and free the workspaces cached by factor() and factor_batched()."""
+    _check(lib().mrcqr_release_cache(), "mrcqr_release_cache")
 
 
 def version() -> int:

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <vector>
 #include <mutex>
 #include <tuple>
@@ -38,6 +39,10 @@ hipError_t launch_rc_tail(const double* Rc, int n, int64_t ldc, const double* Rs
                           double* R, int64_t ldr, const Ctrl* ctrl, int phase, hipStream_t st);
 hipError_t launch_qform(const double* B, int m, int n, int64_t ldb, const double* X, int64_t ldx, double* Q,
                         int64_t ldq, const Ctrl* ctrl, int phase, hipStream_t st);
+hipError_t launch_posterior(const double* Rc, const double* X, int n, int64_t ld, Ctrl* ctrl, int phase,
+                            double* kappa_out, hipStream_t st);
+hipError_t launch_posterior_grouped(const BatchInst* bi, const int32_t* members, int count, const BatchCall& call,
+                                    int phase, hipStream_t st);
 hipError_t launch_ctrl_finalize(const Ctrl* ctrl, void* info, hipStream_t st);
 // grouped launches over the members of a batch
 hipError_t launch_draw_grouped(const BatchInst* bi, const int32_t* members, int count, int max_s,
@@ -148,21 +153,27 @@ static int execute(const mrcqr_plan* p, char* ws, const double* A, int64_t lda, 
     return launch_sketch(pp, A, lda, m, n, S, s, seed, Ypart, Y, s, ctrl, phase, st) == hipSuccess &&
            launch_sketch_qr(pp == P_FP64, Y, s, n, s, Rs, n, nullptr, ctrl, pp, phase, st) == hipSuccess;
   };
+  // Stage 2 and 3 of one pass; Q is formed in the pass's tail phase, which
+  // is skipped when the posterior check asks for a rerun
   auto stage2 = [&](int phase, int tail_phase) -> bool {
     return launch_trsm(A, m, n, lda, Rs, n, B, ldb, Tw, ctrl, phase, st) == hipSuccess &&
            launch_gram(B, m, n, ldb, Gpart, G, n, ctrl, phase, st) == hipSuccess &&
            launch_cholesky(G, n, n, Rc, n, nullptr, nullptr, ctrl, phase, st) == hipSuccess &&
-           launch_rc_tail(Rc, n, n, Rs, n, Rci, n, R, ldr, ctrl, tail_phase, st) == hipSuccess &&
+           launch_rc_tail(Rc, n, n, Rs, n, Rci, n, R, ldr, ctrl, phase, st) == hipSuccess &&
+           launch_posterior(Rc, Rci, n, n, ctrl, phase, nullptr, st) == hipSuccess &&
            launch_qform(B, m, n, ldb, Rci, n, Q, ldq, ctrl, tail_phase, st) == hipSuccess;
   };
   if (automode) {
     for (int pp : {P_FP16, P_FP32, P_FP64})
       if (!stage1(pp, PH_FIRST)) return MRCQR_ERR_DEVICE;
     if (!stage2(PH_FIRST, PH_FIRST_TAIL)) return MRCQR_ERR_DEVICE;
-    // rerun pass, enabled on the device by the posterior check
+    // rerun passes, enabled on the device by the posterior check (at most
+    // two: FP16 -> FP32 -> FP64)
     for (int pp : {P_FP32, P_FP64})
       if (!stage1(pp, PH_RERUN)) return MRCQR_ERR_DEVICE;
-    if (!stage2(PH_RERUN, PH_RERUN)) return MRCQR_ERR_DEVICE;
+    if (!stage2(PH_RERUN, PH_RERUN_TAIL)) return MRCQR_ERR_DEVICE;
+    if (!stage1(P_FP64, PH_RERUN2)) return MRCQR_ERR_DEVICE;
+    if (!stage2(PH_RERUN2, PH_RERUN2)) return MRCQR_ERR_DEVICE;
   } else {
     if (!stage1(prec, PH_FIRST)) return MRCQR_ERR_DEVICE;
     if (!stage2(PH_FIRST, PH_FIRST)) return MRCQR_ERR_DEVICE;
@@ -306,23 +317,37 @@ static int batch_execute(const mrcqr_batch_plan* p, const BatchCall& call, hipSt
       ok = ok && launch_gram_grouped(g.key, bi, p->d_members + g.off, g.count, g.max_a, g.max_b, call, phase, st) ==
                      hipSuccess;
     ok = ok && launch_cholesky_grouped(bi, all, nb, call, phase, st) == hipSuccess;
-    ok = ok && launch_rc_tail_grouped(bi, all, nb, p->max_n, call, tail, st) == hipSuccess;
+    ok = ok && launch_rc_tail_grouped(bi, all, nb, p->max_n, call, phase, st) == hipSuccess;
+    ok = ok && launch_posterior_grouped(bi, all, nb, call, phase, st) == hipSuccess;
     for (const BatchGroup& g : p->qform)
       ok = ok && launch_qform_grouped(g.key, bi, p->d_members + g.off, g.count, g.max_b, call, tail, st) == hipSuccess;
   };
   for (int pp : {P_FP16, P_BF16, P_FP32, P_FP64}) stage1(pp, PH_FIRST);
   stage2(PH_FIRST, PH_FIRST_TAIL);
   for (int pp : {P_FP32, P_FP64}) stage1(pp, PH_RERUN);
-  stage2(PH_RERUN, PH_RERUN);
+  stage2(PH_RERUN, PH_RERUN_TAIL);
+  stage1(P_FP64, PH_RERUN2);
+  stage2(PH_RERUN2, PH_RERUN2);
   if (call.info) ok = ok && launch_finalize_grouped(bi, all, nb, call, st) == hipSuccess;
   return ok ? MRCQR_OK : MRCQR_ERR_DEVICE;
 }
 
 // ---- plan cache for mrcqr_factor ----
+// One workspace per (device, m, n, s). Calls of one shape are serialized on
+// the device: each call's stream waits for the previous call's completion
+// event on that workspace before its first kernel (no host wait), so calls
+// from different streams or host threads never overlap on it. The entries
+// live until mrcqr_release_cache().
 namespace {
-struct CacheEntry { mrcqr_plan plan; void* ws; };
+struct CacheEntry {
+  mrcqr_plan plan;
+  void* ws = nullptr;
+  hipEvent_t done = nullptr;
+  bool used = false;
+  std::mutex mu;
+};
 std::mutex g_mu;
-std::map<std::tuple<int, int64_t, int64_t, int64_t>, CacheEntry> g_cache;
+std::map<std::tuple<int, int64_t, int64_t, int64_t>, std::unique_ptr<CacheEntry>> g_cache;
 // mrcqr_factor_batched: plan, workspace and per-call argument arrays per
 // (device, shape list)
 struct BatchEntry {
@@ -334,6 +359,11 @@ struct BatchEntry {
 };
 std::mutex g_batch_mu;
 std::map<std::vector<int64_t>, BatchEntry> g_batch_cache;
+
+bool stream_capturing(hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+}
 }  // namespace
 
 extern "C" {
@@ -378,6 +408,8 @@ int mrcqr_regime_reset(const mrcqr_plan* plan, void* workspace, size_t workspace
 int mrcqr_factor(const double* A, int64_t m, int64_t n, int64_t lda, int sketch_precision, uint64_t seed,
                  int64_t s, double* Q, int64_t ldq, double* R, int64_t ldr, void* stream, mrcqr_info* info_dev) {
   if (s == 0) s = 2 * n;
+  // the carried precision needs a workspace owned by the caller (plan API)
+  if (sketch_precision == MRCQR_PREC_AUTO_CARRY) return MRCQR_ERR_ARG;
   const int c = check_factor_args(A, m, n, lda, sketch_precision, s, Q, ldq, R, ldr);
   if (c) return c;
   int dev = 0;
@@ -388,21 +420,60 @@ int mrcqr_factor(const double* A, int64_t m, int64_t n, int64_t lda, int sketch_
     auto key = std::make_tuple(dev, m, n, s);
     auto it = g_cache.find(key);
     if (it == g_cache.end()) {
-      CacheEntry ce;
-      ce.plan.m = m; ce.plan.n = n; ce.plan.s = s;
-      plan_layout(&ce.plan);
-      if (hipMalloc(&ce.ws, ce.plan.total) != hipSuccess) return MRCQR_ERR_DEVICE;
-      // no AUTO_CARRY record yet: the control block starts as zero bytes
-      if (hipMemset(ce.ws, 0, sizeof(Ctrl)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
-        (void)hipFree(ce.ws);
+      std::unique_ptr<CacheEntry> ce(new CacheEntry());
+      ce->plan.m = m; ce->plan.n = n; ce->plan.s = s;
+      plan_layout(&ce->plan);
+      if (hipMalloc(&ce->ws, ce->plan.total) != hipSuccess) return MRCQR_ERR_DEVICE;
+      if (hipEventCreateWithFlags(&ce->done, hipEventDisableTiming) != hipSuccess) {
+        (void)hipFree(ce->ws);
         return MRCQR_ERR_DEVICE;
       }
-      it = g_cache.emplace(key, ce).first;
+      it = g_cache.emplace(key, std::move(ce)).first;
     }
-    ent = &it->second;
+    ent = it->second.get();
   }
-  return execute(&ent->plan, static_cast<char*>(ent->ws), A, lda, sketch_precision, seed, Q, ldq, R, ldr,
-                 as_stream(stream), info_dev);
+  const hipStream_t st = as_stream(stream);
+  std::lock_guard<std::mutex> lk(ent->mu);
+  // Under stream capture the event edges are left out (an event recorded
+  // outside the capture cannot be waited on inside it); a captured call
+  // shares the workspace with every other call of its shape.
+  const bool capturing = stream_capturing(st);
+  if (ent->used && !capturing && hipStreamWaitEvent(st, ent->done, 0) != hipSuccess) return MRCQR_ERR_DEVICE;
+  const int r = execute(&ent->plan, static_cast<char*>(ent->ws), A, lda, sketch_precision, seed, Q, ldq, R, ldr,
+                        st, info_dev);
+  if (!capturing) {
+    // recorded even after a failed launch: kernels enqueued before it may
+    // still use the workspace
+    if (hipEventRecord(ent->done, st) != hipSuccess) return MRCQR_ERR_DEVICE;
+    ent->used = true;
+  }
+  return r;
+}
+
+int mrcqr_release_cache(void) {
+  int rc = MRCQR_OK;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto& kv : g_cache) {
+      CacheEntry& e = *kv.second;
+      std::lock_guard<std::mutex> lk2(e.mu);
+      if (e.used && hipEventSynchronize(e.done) != hipSuccess) rc = MRCQR_ERR_DEVICE;
+      if (hipEventDestroy(e.done) != hipSuccess || hipFree(e.ws) != hipSuccess) rc = MRCQR_ERR_DEVICE;
+    }
+    g_cache.clear();
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    for (auto& kv : g_batch_cache) {
+      BatchEntry& e = kv.second;
+      if (e.used && hipEventSynchronize(e.done) != hipSuccess) rc = MRCQR_ERR_DEVICE;
+      if (hipEventDestroy(e.done) != hipSuccess || hipFree(e.ws) != hipSuccess || hipFree(e.params) != hipSuccess)
+        rc = MRCQR_ERR_DEVICE;
+      batch_plan_free(e.plan);
+    }
+    g_batch_cache.clear();
+  }
+  return rc;
 }
 
 int mrcqr_batch_plan_create(int32_t batch, const int64_t* m, const int64_t* n, mrcqr_batch_plan** out) {
@@ -434,6 +505,7 @@ int mrcqr_factor_batched(int32_t batch, const double* const* A, const int64_t* m
     return MRCQR_ERR_ARG;
   if (batch == 0) return MRCQR_OK;
   for (int32_t i = 0; i < batch; ++i) {
+    if (precision[i] == MRCQR_PREC_AUTO_CARRY) return MRCQR_ERR_ARG;  // needs a caller-owned workspace
     const int c = check_factor_args(A[i], m[i], n[i], lda[i], precision[i], 2 * n[i], Q[i], ldq[i], R[i], ldr[i]);
     if (c) return c;
   }
@@ -453,9 +525,6 @@ int mrcqr_factor_batched(int32_t batch, const double* const* A, const int64_t* m
       batch_plan_free(be.plan);
       return MRCQR_ERR_DEVICE;
     }
-    // no AUTO_CARRY records yet
-    if (hipMemset(be.ws, 0, be.plan->total) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
-      return MRCQR_ERR_DEVICE;
     it = g_batch_cache.emplace(key, be).first;
   }
   BatchEntry& be = it->second;
@@ -559,7 +628,7 @@ int mrcqr_cholesky(const double* G, int64_t n, int64_t ldg, double* Rc, int64_t 
 int mrcqr_trmm(const double* R2, int64_t ld2, const double* R1, int64_t ld1, int64_t n, double* R, int64_t ldr,
                void* stream) {
   if (!R2 || !R1 || !R || n < 1 || ld2 < n || ld1 < n || ldr < n) return MRCQR_ERR_ARG;
-  if (n > 4096) return MRCQR_ERR_UNSUPPORTED;
+  if (n > NMAX) return MRCQR_ERR_UNSUPPORTED;
   return hip_status(launch_trmm(R2, ld2, R1, ld1, (int)n, R, ldr, nullptr, PH_FIRST, as_stream(stream)));
 }
 
@@ -582,11 +651,18 @@ int mrcqr_condest(const double* R, int64_t n, int64_t ldr, double* kappa_dev, vo
   return hip_status(launch_condest(R, (int)n, ldr, kappa_dev, as_stream(stream)));
 }
 
+int mrcqr_posterior_kappa(const double* R, const double* X, int64_t n, int64_t ld, double* kappa_dev,
+                          void* stream) {
+  if (!R || !X || !kappa_dev || n < 1 || ld < n) return MRCQR_ERR_ARG;
+  if (n > NMAX) return MRCQR_ERR_UNSUPPORTED;
+  return hip_status(launch_posterior(R, X, (int)n, ld, nullptr, PH_FIRST, kappa_dev, as_stream(stream)));
+}
+
 const char* mrcqr_status_string(int status) {
   switch (status) {
     case MRCQR_OK: return "ok";
     case MRCQR_ERR_ARG: return "invalid argument";
-    case MRCQR_ERR_NONFINITE: return "non-finite value in the sketch";
+    case MRCQR_ERR_NONFINITE: return "non-finite value in the sketch (non-finite input, or input out of the precision's range)";
     case MRCQR_ERR_CHOL_BREAKDOWN: return "Cholesky breakdown (Gram matrix not numerically positive definite)";
     case MRCQR_ERR_SKETCH_SINGULAR: return "sketch factor Rs is singular or not finite";
     case MRCQR_ERR_WORKSPACE: return "workspace missing or too small";

@@ -1,10 +1,10 @@
 // Algorithm 1, second step: Cholesky factorization G = Rc^T Rc (float64),
 // with breakdown detection (a pivot that is not positive or not finite,
-// the failure mode the paper describes for Cholesky-QR), the posterior
-// condition estimate of Rc = the condition number of A Rs^{-1} (Section
-// "Adaptive Precision Selection": an underestimated precision shows up as
-// lost orthogonality), Stage 3's product R = Rc Rs, and the small
-// per-call control kernels.
+// the failure mode the paper describes for Cholesky-QR), the ICE part of the
+// posterior condition estimate of Rc = the condition number of A Rs^{-1}
+// (Section "Adaptive Precision Selection": an underestimated precision shows
+// up as lost orthogonality; the decision is taken in posterior.hip), Stage
+// 3's product R = Rc Rs, and the small per-call control kernels.
 #include "batch.hpp"
 #include "ice.hpp"
 #include "small.hpp"
@@ -162,24 +162,11 @@ __device__ __forceinline__ void chol_body(
     if (tid == 0) {
       if (fail_out) *fail_out = f;
       if (kappa_out) *kappa_out = kappa;
+      // the posterior kernel combines this estimate with power steps and
+      // takes the rerun decision once Rc^{-1} is formed
       if (ctrl) {
         ctrl->kappa_rc = kappa;
-        const bool bad = (f >= 0) || !(kappa <= TAU_POSTERIOR);
-        const int p = ctrl->cur_prec;
-        if (phase == PH_FIRST && ctrl->auto_mode && bad && ctrl->status == ST_OK &&
-            (p == P_FP16 || p == P_FP32)) {
-          // self-correcting rerun one precision higher (Section "Adaptive
-          // Precision Selection"): the rerun pass is enabled on the device
-          ctrl->retry = 1;
-          ctrl->cur_prec = (p == P_FP16) ? P_FP32 : P_FP64;
-          ctrl->escalations += 1;
-        } else {
-          if (ctrl->status == ST_OK) {
-            if (f >= 0) { ctrl->status = ST_CHOL; ctrl->chol_fail = f; }
-            else if (!(kappa <= TAU_POSTERIOR)) ctrl->status = ST_POSTERIOR;
-          }
-          ctrl_carry_record(ctrl);
-        }
+        ctrl->pass_fail = f;
       }
     }
   }

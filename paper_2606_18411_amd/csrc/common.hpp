@@ -65,15 +65,17 @@ __host__ __device__ __forceinline__ uint64_t hash_at(uint64_t key, uint64_t i) {
 struct Ctrl {
   int32_t cur_prec;     // precision of the Stage-1 attempt that is current
   int32_t status;       // mrcqr_status so far
-  int32_t chol_fail;    // first failing Cholesky pivot or -1
+  int32_t chol_fail;    // first failing Cholesky pivot of the accepted pass or -1
   int32_t escalations;  // AUTO escalations
   int32_t auto_mode;    // AutoMode: how the precision is chosen
-  int32_t retry;        // 1 when the posterior check asked for a rerun
+  int32_t retry;        // reruns the posterior check asked for (0, 1 or 2)
   int32_t carry_prec;   // precision the last carrying call accepted
   int32_t pad0;
   uint64_t carry_tag;   // CARRY_TAG while carry_prec holds a record
   double kappa_rs;
   double kappa_rc;
+  int32_t pass_fail;    // Cholesky breakdown index of the current pass or -1
+  int32_t pad1;
 };
 
 // Precision choice of a call: fixed; AUTO from FP16; AUTO from the
@@ -93,8 +95,9 @@ enum : int32_t {
 // like kappa^2 u, so 20 keeps it near 4e-14.
 constexpr double TAU_FP16 = 1e4;
 constexpr double TAU_FP32 = 1e8;
-constexpr double TAU_BF16 = 1e2;
 constexpr double TAU_POSTERIOR = 20.0;
+// Power steps of the posterior estimate of kappa(Rc) (see posterior.hip).
+constexpr int POSTERIOR_STEPS = 12;
 
 // Start-of-call state of the control block (one thread writes it). The
 // carry record survives; a carrying call starts from it when it is valid.
@@ -111,6 +114,7 @@ __device__ __forceinline__ void ctrl_reset(Ctrl* ctrl, int prec, int auto_mode) 
   ctrl->retry = 0;
   ctrl->kappa_rs = 0.0;
   ctrl->kappa_rc = 0.0;
+  ctrl->pass_fail = -1;
 }
 
 // Called once the call's precision is final: a carrying call leaves it as
@@ -122,19 +126,25 @@ __device__ __forceinline__ void ctrl_carry_record(Ctrl* ctrl) {
   }
 }
 
-// Launch gating of the static launch sequence (no host round trip):
+// Launch gating of the static launch sequence (no host round trip). The
+// posterior check may ask for up to two reruns (FP16 -> FP32 -> FP64):
 //   phase 0: first pass, always runs;
-//   phase 1: rerun pass, runs only when the posterior check asked for it;
-//   phase 2: tail of the first pass (Q and R), skipped when a rerun follows.
+//   phase 1: first rerun pass, runs when at least one rerun was asked for;
+//   phase 2: tail of the first pass (Q), skipped when a rerun follows;
+//   phase 3: second rerun pass (with its tail), runs when two were asked for;
+//   phase 4: tail of the first rerun pass, skipped when a second follows.
 // A Stage-1 kernel for precision slot_prec runs only while that precision
 // is the current one (P_AUTO = any).
-enum Phase : int { PH_FIRST = 0, PH_RERUN = 1, PH_FIRST_TAIL = 2 };
+enum Phase : int { PH_FIRST = 0, PH_RERUN = 1, PH_FIRST_TAIL = 2, PH_RERUN2 = 3, PH_RERUN_TAIL = 4 };
 
 __device__ __forceinline__ bool skip_launch(const Ctrl* ctrl, int slot_prec, int phase) {
   if (ctrl == nullptr) return false;
   if (ctrl->status == ST_ARG) return true;  // a batch member with invalid arguments
-  if (phase == PH_RERUN && !ctrl->retry) return true;
-  if (phase == PH_FIRST_TAIL && ctrl->retry) return true;
+  const int retry = ctrl->retry;
+  if (phase == PH_RERUN && retry < 1) return true;
+  if (phase == PH_FIRST_TAIL && retry != 0) return true;
+  if (phase == PH_RERUN2 && retry < 2) return true;
+  if (phase == PH_RERUN_TAIL && retry != 1) return true;
   return slot_prec != P_AUTO && ctrl->cur_prec != slot_prec;
 }
 

@@ -22,12 +22,15 @@ namespace mrcqr {
 constexpr int QR_THREADS = 1024;
 
 // Condition estimate of Rs (held row-major in LDS) and the AUTO
-// escalation rule, called by every thread after Rs is complete: a singular
-// Rs or an estimate at or above the regime bound of the current precision
-// moves the call one precision up (FP16 -> FP32 -> FP64); a singular Rs
-// with nothing left to escalate to is reported.
-__device__ void sketch_qr_epilogue(const double* Rl, int n, bool bad, double* __restrict__ kappa_out,
+// escalation rule, called by every thread after Rs is complete: a sketch
+// holding inf or NaN, a singular Rs or an estimate at or above the regime
+// bound of the current precision moves the call one precision up (FP16 ->
+// FP32 -> FP64); with nothing left to escalate to, a non-finite sketch
+// (non-finite input, or input beyond the range of the precision) or a
+// singular Rs is reported.
+__device__ void sketch_qr_epilogue(const double* Rl, int n, bool bad, bool nonfinite, double* __restrict__ kappa_out,
                                    Ctrl* __restrict__ ctrl, int want_kappa) {
+  bad = bad || nonfinite;
   const bool auto_here = ctrl != nullptr && ctrl->auto_mode;
   double kappa = ice_kappa_block(Rl, n, n, 1, !bad && (auto_here || want_kappa));
   if (bad) kappa = __builtin_inf();
@@ -37,10 +40,10 @@ __device__ void sketch_qr_epilogue(const double* Rl, int n, bool bad, double* __
   ctrl->kappa_rs = kappa;
   const int p = ctrl->cur_prec;
   const bool can_escalate = ctrl->auto_mode && (p == P_FP16 || p == P_FP32);
-  const double tau_p = (p == P_FP16) ? TAU_FP16 : (p == P_FP32 ? TAU_FP32 : (p == P_BF16 ? TAU_BF16 : __builtin_inf()));
+  const double tau_p = (p == P_FP16) ? TAU_FP16 : (p == P_FP32 ? TAU_FP32 : __builtin_inf());
   if (bad) {
     if (can_escalate) { ctrl->cur_prec = (p == P_FP16) ? P_FP32 : P_FP64; ctrl->escalations += 1; }
-    else ctrl->status = ST_SINGULAR;
+    else ctrl->status = nonfinite ? ST_NONFINITE : ST_SINGULAR;
   } else if (can_escalate && kappa >= tau_p) {
     ctrl->cur_prec = (p == P_FP16) ? P_FP32 : P_FP64;
     ctrl->escalations += 1;
@@ -64,6 +67,7 @@ __global__ __launch_bounds__(NT) void householder_kernel(
   float* dsign = reinterpret_cast<float*>(taus + 2);     // n
   __shared__ int bad_flag;
   __shared__ double wmax[NT / 64];
+  __shared__ int wnf[NT / 64];
 
   // thread -> column c, contiguous row block [rb*RB, rb*RB + RB)
   const int tid = threadIdx.x;
@@ -82,17 +86,20 @@ __global__ __launch_bounds__(NT) void householder_kernel(
   // max magnitude in [0.5, 1); R is scaled back by 2^-es at the end.
   {
     double lm = 0.0;
+    bool nf = false;
 #pragma unroll
-    for (int i = 0; i < RB; ++i) lm = fmax(lm, fabs((double)y[i]));
+    for (int i = 0; i < RB; ++i) { lm = fmax(lm, fabs((double)y[i])); nf = nf || !isfinite(y[i]); }
     // wave max via the group sum machinery is not needed: use LDS per wave
     for (int o = 32; o > 0; o >>= 1) lm = fmax(lm, __shfl_xor(lm, o));
-    if ((tid & 63) == 0) wmax[tid >> 6] = lm;
+    const bool wave_nf = __ballot(nf) != 0;
+    if ((tid & 63) == 0) { wmax[tid >> 6] = lm; wnf[tid >> 6] = wave_nf; }
   }
   __syncthreads();
   int es = 0;
+  bool nonfinite = false;
   {
     double gm = 0.0;
-    for (int w = 0; w < NT / 64; ++w) gm = fmax(gm, wmax[w]);
+    for (int w = 0; w < NT / 64; ++w) { gm = fmax(gm, wmax[w]); nonfinite = nonfinite || wnf[w]; }
     if (gm > 0.0 && isfinite(gm)) { int E; (void)frexp(gm, &E); es = -E; }
   }
 #pragma unroll
@@ -170,7 +177,7 @@ __global__ __launch_bounds__(NT) void householder_kernel(
     }
   }
   __syncthreads();
-  sketch_qr_epilogue(Rl, n, bad_flag != 0, kappa_out, ctrl, want_kappa);
+  sketch_qr_epilogue(Rl, n, bad_flag != 0, nonfinite, kappa_out, ctrl, want_kappa);
 }
 
 
@@ -204,6 +211,7 @@ __device__ __forceinline__ void householder16_body(
   float* dsign = reinterpret_cast<float*>(taus + 2);      // n
   __shared__ int bad_flag;
   __shared__ double wmax[NT / 64];
+  __shared__ int wnf[NT / 64];
 
   const int tid = threadIdx.x, grp = tid / TPG, t = tid % TPG;
   auto row_of = [&](int i, int e) { return VEC * (t + TPG * i) + e; };
@@ -224,18 +232,21 @@ __device__ __forceinline__ void householder16_body(
   // exact power-of-two prescale: max |Y| * 2^es in [0.5, 1)
   {
     double lm = 0.0;
+    bool nf = false;
 #pragma unroll
     for (int k = 0; k < CPT; ++k)
 #pragma unroll
-      for (int i = 0; i < RPT; ++i) lm = fmax(lm, fabs((double)y[k][i]));
+      for (int i = 0; i < RPT; ++i) { lm = fmax(lm, fabs((double)y[k][i])); nf = nf || !isfinite(y[k][i]); }
     for (int o = 32; o > 0; o >>= 1) lm = fmax(lm, __shfl_xor(lm, o));
-    if ((tid & 63) == 0) wmax[tid >> 6] = lm;
+    const bool wave_nf = __ballot(nf) != 0;
+    if ((tid & 63) == 0) { wmax[tid >> 6] = lm; wnf[tid >> 6] = wave_nf; }
   }
   __syncthreads();
   int es = 0;
+  bool nonfinite = false;
   {
     double gm = 0.0;
-    for (int w = 0; w < NT / 64; ++w) gm = fmax(gm, wmax[w]);
+    for (int w = 0; w < NT / 64; ++w) { gm = fmax(gm, wmax[w]); nonfinite = nonfinite || wnf[w]; }
     if (gm > 0.0 && isfinite(gm)) { int E; (void)frexp(gm, &E); es = -E; }
   }
 #pragma unroll
@@ -344,7 +355,7 @@ __device__ __forceinline__ void householder16_body(
       }
   }
   __syncthreads();
-  sketch_qr_epilogue(Rl, n, bad_flag != 0, kappa_out, ctrl, want_kappa);
+  sketch_qr_epilogue(Rl, n, bad_flag != 0, nonfinite, kappa_out, ctrl, want_kappa);
 }
 
 // Stand-alone ICE of an upper-triangular matrix (two waves).

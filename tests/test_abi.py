@@ -60,6 +60,22 @@ def test_argument_errors_are_synchronous(lib):
         assert f(fake, m, n, lda, prec, 0, s, fake2, ldq, fake2, ldr, None, None) == want
     assert f(None, 100, 10, 100, 3, 0, 0, fake2, 100, fake2, 10, None, None) == 1
     assert f(fake, 100, 10, 100, 3, 0, 0, fake, 100, fake2, 10, None, None) == 1  # Q aliases A
+    # AUTO_CARRY needs a caller-owned workspace (plan API)
+    assert f(fake, 100, 10, 100, 5, 0, 0, fake2, 100, fake2, 10, None, None) == 1
+
+
+def test_step_entry_points_reject_shapes_synchronously(lib):
+    vp, i64 = ctypes.c_void_p, ctypes.c_int64
+    fake = ctypes.c_void_p(0x1000)
+    lib.mrcqr_trmm.argtypes = [vp, i64, vp, i64, i64, vp, i64, vp]
+    assert lib.mrcqr_trmm(fake, 200, fake, 200, 200, fake, 200, None) == 8
+    assert lib.mrcqr_trmm(fake, 10, fake, 10, 11, fake, 11, None) == 1
+    lib.mrcqr_posterior_kappa.argtypes = [vp, vp, i64, i64, vp, vp]
+    assert lib.mrcqr_posterior_kappa(fake, fake, 200, 200, fake, None) == 8
+    assert lib.mrcqr_posterior_kappa(fake, None, 20, 20, fake, None) == 1
+    assert lib.mrcqr_posterior_kappa(fake, fake, 20, 19, fake, None) == 1
+    # nothing cached in this process: releasing touches no device
+    assert lib.mrcqr_release_cache() == 0
 
 
 def test_status_strings(lib):

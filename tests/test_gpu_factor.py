@@ -131,11 +131,62 @@ def test_zero_column_reports_singular_sketch(M):
     assert info.status == 4
 
 
-def test_nonfinite_input_is_reported(M):
+@pytest.mark.parametrize("bad", [np.nan, np.inf])
+@pytest.mark.parametrize("prec", ["fp16", "fp64", "auto"])
+def test_nonfinite_input_is_reported(M, bad, prec):
     A = W.gaussian(4096, 16, 10)
-    A[100, 3] = np.nan
+    A[100, 3] = bad
+    _, _, info = M.factor(to_dev(A), prec, seed=1)
+    assert info.status == M.ERR_NONFINITE, info
+    if prec == "auto":  # escalated through every precision before reporting
+        assert info.precision == "fp64" and info.escalations == 2, info
+
+
+def test_out_of_range_input_escalates_to_a_wider_sketch(M):
+    """Entries near 2^118 leave binary16's range even after the block
+    prescale (the exponent shift is clamped at 100, so they stay near 2^18 >
+    65504): the FP16 sketch is not finite, AUTO escalates, and FP32 (8
+    exponent bits) forms it."""
+    A = W.test_matrix(4096, 16, 1e2, 11) * 2.0 ** 124
     _, _, info = M.factor(to_dev(A), "fp16", seed=1)
-    assert info.status in (3, 4)
+    assert info.status == M.ERR_NONFINITE, info
+    Q, R, info = M.factor(to_dev(A), "auto", seed=1)
+    assert info.status == 0 and info.precision == "fp32" and info.escalations == 1, info
+    assert MT.orthogonality(to_host(Q)) <= 1e-13
+
+
+@pytest.mark.parametrize("s,seed", [(17, 0), (18, 26)])
+def test_posterior_rerun_ladder_matches_oracle(M, s, seed):
+    """A sketch barely taller than n leaves kappa(Rc) above the posterior
+    bound at every precision: AUTO reruns at FP32, then FP64, and reports the
+    posterior warning, as the oracle does (same decision, same estimate)."""
+    A = W.test_matrix(2048, 16, 1e2, 3)
+    progress(f"posterior ladder s={s} seed={seed}")
+    Q, R, info = M.factor(to_dev(A), "auto", seed=seed, s=s)
+    o = OM.factor(A, OM.AUTO, seed, s=s)
+    assert (info.status, P.NAMES[info.precision_used], info.escalations) == (o.status, "fp64", 2), (info, o.status)
+    assert abs(info.kappa_rc_est - o.kappa_rc) <= 1e-6 * o.kappa_rc
+    assert MT.residual(A, to_host(Q), to_host(R), 1.0) <= 1e-13
+
+
+def test_concurrent_streams_same_shape(M):
+    """Calls of one shape from two streams share the cached workspace; the
+    library orders them on the device, so each result is bitwise that of a
+    call made alone."""
+    mats = [to_dev(W.test_matrix(30000, 48, 1e5, 1200 + i)) for i in range(4)]
+    ref = [M.factor(a, "auto", seed=7) for a in mats]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for st in streams:
+        st.wait_stream(torch.cuda.current_stream())
+    outs = []
+    for i, a in enumerate(mats):
+        st = streams[i % 2]
+        with torch.cuda.stream(st):
+            outs.append(M.factor(a, "auto", seed=7, stream=st, sync=False))
+    torch.cuda.synchronize()
+    for (Q, R, info), (Qr, Rr, ir) in zip(outs, ref):
+        assert torch.equal(Q, Qr) and torch.equal(R, Rr)
+        assert M.read_infos(info)[0] == ir
 
 
 def test_plan_execute_matches_factor(M):

@@ -6,12 +6,12 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle import cholqr as CQ, householder as HH, metrics as MT, precision as P, rng, sketch as SK
+from oracle import cholqr as CQ, householder as HH, metrics as MT, mrcqr as OM, precision as P, rng, sketch as SK
 from gpu_common import require_gpu, to_dev, to_host, progress, torch
 
 U32 = 2.0 ** -24
 # same bounds as the small-size sketch parity test
-SKETCH_TOL = {P.FP64: 2e-12, P.FP16: 2e-5}
+SKETCH_TOL = {P.FP64: 2e-12, P.FP32: 200 * U32, P.FP16: 2e-5, P.BF16: 1.6e-4}
 
 pytestmark = pytest.mark.gpu
 
@@ -46,10 +46,12 @@ def test_headline_shape(M, big, prec):
     assert np.max(np.abs(Qh[rows] - U[rows] @ Qt)) <= tol
 
 
-@pytest.mark.parametrize("prec,name", [(P.FP16, "fp16"), (P.FP64, "fp64")])
-def test_headline_sketch_sampled_rows(M, big, prec, name):
-    """Full-size sketch in the bench's launch configuration; 3 of the s = 256
-    sampled rows (first, middle, last) against the oracle, elementwise."""
+@pytest.mark.parametrize("prec,name", [(P.FP16, "fp16"), (P.BF16, "bf16"), (P.FP32, "fp32"), (P.FP64, "fp64")])
+def test_headline_sketch_all_rows(M, big, prec, name):
+    """Full-size sketch in the bench's launch configuration: all s = 256
+    sampled rows against the oracle, elementwise, in every precision (each
+    row chunk holds 64 panels, so the coefficient re-seeding every 8 panels
+    of the half-width sketches is exercised throughout)."""
     A = big[0]
     m, n = A.shape
     s, seed = 2 * n, 5
@@ -57,15 +59,18 @@ def test_headline_sketch_sampled_rows(M, big, prec, name):
     S = rng.sample_rows(seed, m, s)
     assert np.array_equal(to_host(M.draw(seed, m, s)), S)
     Y = to_host(M.sketch(to_dev(A), torch.from_numpy(S.astype(np.int32)).cuda(), seed, name))
-    pick = np.array([0, s // 2, s - 1])
     d = rng.signs(seed, m)
-    Yo = SK.sketch(A, S[pick], d, prec, s_total=s)
-    bound = SK.sketch_abs_bound(A, S[pick], d, prec, s_total=s)
+    Yo = SK.sketch(A, S, d, prec, s_total=s)
+    bound = SK.sketch_abs_bound(A, S, d, prec, s_total=s)
     tol = SKETCH_TOL[prec] * bound + (U32 * np.abs(Yo) if prec != P.FP64 else 0)
-    assert np.all(np.abs(Y[pick] - Yo) <= tol)
+    err = np.abs(Y - Yo)
+    assert np.all(err <= tol), (np.unravel_index(np.argmax(err - tol), err.shape), float(np.max(err / bound)))
 
 
 def test_headline_shape_auto(M, big):
+    """AUTO at the headline shape (kappa = 1e4, the edge of the half regime)
+    lands where the oracle's AUTO lands on the same seed, with the same
+    escalations and estimates."""
     A, U, Qt, Rt, kappa = big
     progress("full size auto")
     Q, R, info = M.factor(to_dev(A), "auto", seed=4)
@@ -73,6 +78,12 @@ def test_headline_shape_auto(M, big):
     Qh, Rh = to_host(Q), to_host(R)
     assert MT.orthogonality(Qh) <= 1e-13
     assert MT.residual(A, Qh, Rh, 1.0) <= 1e-13
+    progress("full size auto: oracle")
+    o = OM.factor(A, OM.AUTO, seed=4)
+    assert (info.status, info.precision_used, info.escalations) == (o.status, o.precision_used, o.escalations), o
+    # the two float32 sketch QRs round differently (about n u32 kappa apart)
+    assert abs(info.kappa_rs_est - o.kappa_rs) <= 1e-3 * o.kappa_rs
+    assert info.precision == "fp16", info
 
 
 def test_headline_solve_and_form_q_sampled_rows(M, big):

@@ -91,6 +91,18 @@ def test_condest_matches_oracle_ice(M, n, kappa):
     assert abs(k - CE.kappa_est(R)) <= 1e-9 * CE.kappa_est(R)
 
 
+@pytest.mark.parametrize("n,kappa", [(8, 3.0), (16, 40.0), (50, 1e3), (128, 25.0), (128, 1e8)])
+def test_posterior_power_estimate_matches_oracle(M, n, kappa):
+    """Power-step part of the posterior estimate (12 steps on R^T R and
+    X^T X from the normalized all-ones vector) against the oracle's."""
+    R = W.upper_triangular(n, kappa, 60 + n)
+    X = M.tri_inverse(to_dev(R))
+    k = float(to_host(M.posterior_kappa(to_dev(R), X))[0])
+    ko = CE.power_norm(R) * CE.power_norm(to_host(X))
+    assert abs(k - ko) <= 1e-10 * ko
+    assert k <= np.linalg.cond(R) * (1 + 1e-10)
+
+
 @pytest.mark.parametrize("m,n,kappa", [(1000, 8, 1e2), (1000, 20, 1e6), (4096, 32, 1e8), (777, 50, 1e4),
                                        (5000, 64, 1e10), (70001, 100, 1e6), (4097, 128, 1e12), (1, 1, 1.0)])
 def test_trsm_matches_substitution(M, m, n, kappa):
