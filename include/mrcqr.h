@@ -142,6 +142,26 @@ int mrcqr_factor(const double* A, int64_t m, int64_t n, int64_t lda,
                  double* Q, int64_t ldq, double* R, int64_t ldr,
                  void* stream, mrcqr_info* info_dev);
 
+/* mrcqr_factor for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, kernels and results (bitwise) as mrcqr_factor; the
+ * workspace is a fixed device array of
+ * mrcqr_factor_noalloc_max_workspace_bytes() bytes (64 MiB) that the
+ * library holds on every GPU it runs on until the process ends. It calls no
+ * hipMalloc, hipFree or allocating library routine. A shape whose
+ * workspace (mrcqr_plan_workspace_bytes of its plan) exceeds that size
+ * returns MRCQR_ERR_WORKSPACE before anything is launched; n <= 64 with
+ * m up to about 65536 fits. All calls on one GPU share the array: calls
+ * that overlap on the device (other streams, other host threads, or graph
+ * replays running at the same time) race and must be ordered by the caller.
+ * Nothing in the array needs to start at zero, so it keeps whatever the
+ * last call left. AUTO_CARRY is rejected (MRCQR_ERR_ARG). */
+int mrcqr_factor_noalloc(const double* A, int64_t m, int64_t n, int64_t lda,
+                         int sketch_precision, uint64_t seed, int64_t s,
+                         double* Q, int64_t ldq, double* R, int64_t ldr,
+                         void* stream, mrcqr_info* info_dev);
+size_t mrcqr_factor_noalloc_max_workspace_bytes(void);
+
 /* Wait for and free the workspaces cached by mrcqr_factor and
  * mrcqr_factor_batched on every device. No call of those may run
  * concurrently with it. Returns MRCQR_ERR_DEVICE if a HIP call failed. */

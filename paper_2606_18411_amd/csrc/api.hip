@@ -360,6 +360,28 @@ struct BatchEntry {
 std::mutex g_batch_mu;
 std::map<std::vector<int64_t>, BatchEntry> g_batch_cache;
 
+// Workspace of mrcqr_factor_noalloc: a file-scope device array, one copy on
+// every GPU the library runs on, held until the process ends. Host code
+// never uses the array's name as an address: the first call on a device
+// looks up that device's copy with hipGetSymbolAddress and keeps it.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// The calling thread's current device's copy of `scratch` (nullptr on error).
+void* scratch_for_device(int dev) {
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || ptr == nullptr) return nullptr;
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
 bool stream_capturing(hipStream_t st) {
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   return hipStreamIsCapturing(st, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
@@ -449,6 +471,30 @@ int mrcqr_factor(const double* A, int64_t m, int64_t n, int64_t lda, int sketch_
   }
   return r;
 }
+
+int mrcqr_factor_noalloc(const double* A, int64_t m, int64_t n, int64_t lda, int sketch_precision, uint64_t seed,
+                         int64_t s, double* Q, int64_t ldq, double* R, int64_t ldr, void* stream,
+                         mrcqr_info* info_dev) {
+  if (s == 0) s = 2 * n;
+  // the carried precision needs a workspace owned by the caller (plan API)
+  if (sketch_precision == MRCQR_PREC_AUTO_CARRY) return MRCQR_ERR_ARG;
+  const int c = check_factor_args(A, m, n, lda, sketch_precision, s, Q, ldq, R, ldr);
+  if (c) return c;
+  mrcqr_plan plan;
+  plan.m = m; plan.n = n; plan.s = s;
+  plan_layout(&plan);
+  if (plan.total > NOALLOC_SCRATCH_BYTES) return MRCQR_ERR_WORKSPACE;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return MRCQR_ERR_DEVICE;
+  void* ws = scratch_for_device(dev);
+  if (!ws) return MRCQR_ERR_DEVICE;
+  // Nothing in the workspace has to start at zero: the draw kernel resets
+  // the control block, and every partial sum is written before it is read.
+  return execute(&plan, static_cast<char*>(ws), A, lda, sketch_precision, seed, Q, ldq, R, ldr, as_stream(stream),
+                 info_dev);
+}
+
+size_t mrcqr_factor_noalloc_max_workspace_bytes(void) { return NOALLOC_SCRATCH_BYTES; }
 
 int mrcqr_release_cache(void) {
   int rc = MRCQR_OK;
