@@ -142,6 +142,21 @@ int mrcqr_factor(const double* A, int64_t m, int64_t n, int64_t lda,
                  double* Q, int64_t ldq, double* R, int64_t ldr,
                  void* stream, mrcqr_info* info_dev);
 
+/* CholQR2, the unpreconditioned baseline of the paper's stability sweep
+ * (Section "Numerical Stability"): Algorithm 1 applied twice, [Q1, R1] =
+ * CholQR(A), [Q, R2] = CholQR(Q1), R = R2 R1, every step in float64 on the
+ * library's kernels (Gram SYRK, Cholesky, substitution Q = A R^{-1}). It
+ * breaks down once the Gram matrix of A is not numerically positive definite
+ * (kappa(A) past about 1e8): info->status = MRCQR_ERR_CHOL_BREAKDOWN with the
+ * first failing pivot (of pass 1, else of pass 2), and Q, R unspecified.
+ * Needs mrcqr_cholqr2_workspace_bytes(m, n) bytes of device workspace (Q1
+ * and small n x n terms; about m n 8 bytes). Same shape limits as
+ * mrcqr_factor; Q must not overlap A. info_dev may be NULL. */
+size_t mrcqr_cholqr2_workspace_bytes(int64_t m, int64_t n);
+int mrcqr_cholqr2(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, int64_t ldq,
+                  double* R, int64_t ldr, void* workspace, size_t workspace_bytes, void* stream,
+                  mrcqr_info* info_dev);
+
 /* mrcqr_factor for callers that cannot allocate device memory: code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
  * Same arguments, kernels and results (bitwise) as mrcqr_factor; the

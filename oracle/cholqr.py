@@ -80,3 +80,20 @@ def form_q(B: np.ndarray, X: np.ndarray) -> np.ndarray:
 def trmm_upper(R2: np.ndarray, Rs: np.ndarray) -> np.ndarray:
     """R = R2 Rs (product of upper-triangular factors, Stage 3)."""
     return np.triu(np.asarray(R2) @ np.asarray(Rs))
+
+
+def cholqr(A: np.ndarray):
+    """Algorithm 1 (CholQR) on A itself: G = A^T A, G = R^T R, Q = A R^{-1}
+    by substitution. Raises CholeskyBreakdown when the Gram matrix is not
+    numerically positive definite."""
+    R = cholesky_upper(gram(A))
+    return trsm_right_upper(A, R), R
+
+
+def cholqr2(A: np.ndarray):
+    """CholQR2: Algorithm 1 applied twice, R = R2 R1 (the paper's stability
+    baseline in Section "Numerical Stability", which breaks down once the
+    Gram matrix of A loses positive definiteness, kappa(A) past about 1e8)."""
+    Q1, R1 = cholqr(A)
+    Q, R2 = cholqr(Q1)
+    return Q, trmm_upper(R2, R1)

@@ -61,6 +61,8 @@ def lib() -> ctypes.CDLL:
             "mrcqr_sketch_qr": (i32, [vp, i64, i64, i64, i32, vp, i64, vp, vp]),
             "mrcqr_trsm_workspace_bytes": (sz, [i64]),
             "mrcqr_trsm": (i32, [vp, i64, i64, i64, vp, i64, vp, i64, vp, sz, vp]),
+            "mrcqr_cholqr2_workspace_bytes": (sz, [i64, i64]),
+            "mrcqr_cholqr2": (i32, [vp, i64, i64, i64, vp, i64, vp, i64, vp, sz, vp, vp]),
             "mrcqr_gram_workspace_bytes": (sz, [i64, i64]),
             "mrcqr_gram": (i32, [vp, i64, i64, i64, vp, i64, vp, sz, vp]),
             "mrcqr_cholesky": (i32, [vp, i64, i64, vp, i64, vp, vp, vp]),
@@ -199,6 +201,26 @@ def factor(A: torch.Tensor, precision="fp16", seed: int = 0, s: int | None = Non
     code = lib().mrcqr_factor(A.data_ptr(), m, n, _ld(A), _prec(precision), seed & (2 ** 64 - 1), s or 0,
                               Q.data_ptr(), _ld(Q), R.data_ptr(), _ld(R), _stream(stream), info.data_ptr())
     _check(code, "mrcqr_factor")
+    if not sync:
+        return Q, R, info
+    torch.cuda.synchronize(A.device)
+    return Q, R, read_infos(info)[0]
+
+
+def cholqr2(A: torch.Tensor, stream=None, sync: bool = True):
+    """CholQR2 (Algorithm 1 twice), the paper's stability baseline.
+    Returns (Q, R, Info)."""
+    if not isinstance(A, torch.Tensor) or A.dim() != 2:
+        raise ValueError("A must be a 2-D tensor")
+    m, n = A.shape
+    _mat(A, m, n, "A")
+    _same_cuda_device([("A", A)])
+    Q, R = empty_colmajor(m, n, A.device), empty_colmajor(n, n, A.device)
+    wsb = int(lib().mrcqr_cholqr2_workspace_bytes(m, n))
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=A.device)
+    info = torch.empty(INFO_BYTES, dtype=torch.uint8, device=A.device)
+    _check(lib().mrcqr_cholqr2(A.data_ptr(), m, n, _ld(A), Q.data_ptr(), _ld(Q), R.data_ptr(), _ld(R),
+                               ws.data_ptr(), wsb, _stream(stream), info.data_ptr()), "mrcqr_cholqr2")
     if not sync:
         return Q, R, info
     torch.cuda.synchronize(A.device)

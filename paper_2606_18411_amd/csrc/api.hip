@@ -44,6 +44,7 @@ hipError_t launch_posterior(const double* Rc, const double* X, int n, int64_t ld
 hipError_t launch_posterior_grouped(const BatchInst* bi, const int32_t* members, int count, const BatchCall& call,
                                     int phase, hipStream_t st);
 hipError_t launch_ctrl_finalize(const Ctrl* ctrl, void* info, hipStream_t st);
+hipError_t launch_cholqr2_finalize(const int32_t* fail, void* info, hipStream_t st);
 // grouped launches over the members of a batch
 hipError_t launch_draw_grouped(const BatchInst* bi, const int32_t* members, int count, int max_s,
                                const BatchCall& call, hipStream_t st);
@@ -702,6 +703,59 @@ int mrcqr_posterior_kappa(const double* R, const double* X, int64_t n, int64_t l
   if (!R || !X || !kappa_dev || n < 1 || ld < n) return MRCQR_ERR_ARG;
   if (n > NMAX) return MRCQR_ERR_UNSUPPORTED;
   return hip_status(launch_posterior(R, X, (int)n, ld, nullptr, PH_FIRST, kappa_dev, as_stream(stream)));
+}
+
+// CholQR2 (Algorithm 1 twice): workspace = G, R1, R2 (n x n each), the
+// Gram partials, the solve's operand staging, two breakdown indices, Q1.
+struct Cholqr2Layout {
+  size_t G, R1, R2, Gpart, Tw, fail, Q1, total;
+};
+static Cholqr2Layout cholqr2_layout(int64_t m, int64_t n) {
+  Cholqr2Layout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes); return at; };
+  L.G = take((size_t)n * n * sizeof(double));
+  L.R1 = take((size_t)n * n * sizeof(double));
+  L.R2 = take((size_t)n * n * sizeof(double));
+  L.Gpart = take(gram_partial_bytes(m, n));
+  L.Tw = take(trsm_workspace_bytes((int)n));
+  L.fail = take(2 * sizeof(int32_t));
+  L.Q1 = take((size_t)m * n * sizeof(double));
+  L.total = o;
+  return L;
+}
+
+size_t mrcqr_cholqr2_workspace_bytes(int64_t m, int64_t n) {
+  if (n < 1 || m < n || n > NMAX || m >= MMAX) return 0;
+  return cholqr2_layout(m, n).total;
+}
+
+int mrcqr_cholqr2(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, int64_t ldq, double* R,
+                  int64_t ldr, void* workspace, size_t workspace_bytes, void* stream, mrcqr_info* info_dev) {
+  if (!A || !Q || !R || n < 1 || m < n || lda < m || ldq < m || ldr < n || A == Q) return MRCQR_ERR_ARG;
+  if (n > NMAX || m >= MMAX) return MRCQR_ERR_UNSUPPORTED;
+  const Cholqr2Layout L = cholqr2_layout(m, n);
+  if (!workspace || workspace_bytes < L.total) return MRCQR_ERR_WORKSPACE;
+  char* ws = static_cast<char*>(workspace);
+  double* G = reinterpret_cast<double*>(ws + L.G);
+  double* R1 = reinterpret_cast<double*>(ws + L.R1);
+  double* R2 = reinterpret_cast<double*>(ws + L.R2);
+  double* Gpart = reinterpret_cast<double*>(ws + L.Gpart);
+  int32_t* fail = reinterpret_cast<int32_t*>(ws + L.fail);
+  double* Q1 = reinterpret_cast<double*>(ws + L.Q1);
+  const hipStream_t st = as_stream(stream);
+  const int mi = (int)m, ni = (int)n;
+  // pass 1: [Q1, R1] = CholQR(A); pass 2: [Q, R2] = CholQR(Q1); R = R2 R1
+  const bool ok =
+      launch_gram(A, mi, ni, lda, Gpart, G, n, nullptr, PH_FIRST, st) == hipSuccess &&
+      launch_cholesky(G, ni, n, R1, n, fail, nullptr, nullptr, PH_FIRST, st) == hipSuccess &&
+      launch_trsm(A, mi, ni, lda, R1, n, Q1, m, ws + L.Tw, nullptr, PH_FIRST, st) == hipSuccess &&
+      launch_gram(Q1, mi, ni, m, Gpart, G, n, nullptr, PH_FIRST, st) == hipSuccess &&
+      launch_cholesky(G, ni, n, R2, n, fail + 1, nullptr, nullptr, PH_FIRST, st) == hipSuccess &&
+      launch_trsm(Q1, mi, ni, m, R2, n, Q, ldq, ws + L.Tw, nullptr, PH_FIRST, st) == hipSuccess &&
+      launch_trmm(R2, n, R1, n, ni, R, ldr, nullptr, PH_FIRST, st) == hipSuccess &&
+      (!info_dev || launch_cholqr2_finalize(fail, info_dev, st) == hipSuccess);
+  return ok ? MRCQR_OK : MRCQR_ERR_DEVICE;
 }
 
 const char* mrcqr_status_string(int status) {

@@ -232,6 +232,26 @@ __global__ void ctrl_finalize_grouped(const BatchInst* __restrict__ bi, const in
   }
 }
 
+// Outcome of CholQR2 (two Cholesky factorizations, fail[0] and fail[1]):
+// breakdown of the first pass, else of the second (its index is a pivot of
+// the Gram matrix of Q1), else ok.
+__global__ void cholqr2_finalize_kernel(const int32_t* __restrict__ fail, InfoOut* __restrict__ info) {
+  if (threadIdx.x == 0) {
+    const int f = fail[0] >= 0 ? fail[0] : fail[1];
+    info->status = f >= 0 ? ST_CHOL : ST_OK;
+    info->precision_used = P_FP64;
+    info->chol_fail_index = f;
+    info->escalations = 0;
+    info->kappa_rs_est = __builtin_nan("");
+    info->kappa_rc_est = __builtin_nan("");
+  }
+}
+
+hipError_t launch_cholqr2_finalize(const int32_t* fail, void* info, hipStream_t st) {
+  hipLaunchKernelGGL(cholqr2_finalize_kernel, dim3(1), dim3(64), 0, st, fail, (InfoOut*)info);
+  return hipGetLastError();
+}
+
 hipError_t launch_cholesky_grouped(const BatchInst* bi, const int32_t* members, int count, const BatchCall& call,
                                    int phase, hipStream_t st) {
   hipLaunchKernelGGL(chol_grouped, dim3(1, count), dim3(CH_THREADS), 0, st, bi, members, call, phase);

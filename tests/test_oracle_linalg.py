@@ -253,3 +253,42 @@ def test_posterior_estimate_is_a_tight_lower_bound(kappa):
         est = CE.kappa_posterior(R, X)
         assert CE.kappa_est(R) <= est <= k2 * (1 + 1e-10)
         assert est >= 0.6 * k2
+
+
+def test_cholqr_matches_householder_on_well_conditioned_input():
+    A = W.test_matrix(3000, 12, 1e3, 70)
+    Q, R = CQ.cholqr2(A)
+    Qh, Rh = HH.householder_qr(A)
+    assert MT.rel_diff(R, Rh) < 50 * 12 * 2.0 ** -53 * 1e3
+    assert np.max(np.abs(Q - Qh)) < 50 * 12 * 2.0 ** -53 * 1e3
+    assert MT.orthogonality(Q) < 1e-14
+
+
+def test_cholqr_single_pass_loses_orthogonality_like_kappa_squared():
+    # one pass of Algorithm 1 leaves I - Q^T Q ~ kappa^2 u; the second pass
+    # brings it back to ~u (the reason CholQR2 exists)
+    A = W.test_matrix(4000, 10, 1e5, 71)
+    Q1, _ = CQ.cholqr(A)
+    Q2, _ = CQ.cholqr2(A)
+    o1, o2 = MT.orthogonality(Q1), MT.orthogonality(Q2)
+    assert 1e-9 < o1 < 1e-3
+    assert o2 < 1e-14
+
+
+def test_cholqr2_breaks_down_on_a_numerically_singular_gram():
+    # sigma_min^2 / sigma_max^2 = 1e-24 is below the float64 resolution of
+    # the Gram matrix: a pivot of the Cholesky factorization is not positive
+    A = W.paper_sweep_matrix(2000, 20, 1e12, 72)
+    with pytest.raises(CQ.CholeskyBreakdown):
+        CQ.cholqr2(A)
+    B = W.gaussian(500, 6, 73)
+    B[:, 4] = 0.0  # exactly rank deficient: row and pivot 4 of the Gram are zero
+    with pytest.raises(CQ.CholeskyBreakdown) as e:
+        CQ.cholqr(B)
+    assert e.value.index == 4
+
+
+def test_paper_sweep_matrix_has_the_stated_spectrum():
+    A = W.paper_sweep_matrix(4096, 50, 1e10, 74)
+    sv = np.linalg.svd(A, compute_uv=False)
+    assert abs(sv[0] / 1e5 - 1) < 1e-12 and abs(sv[-1] / 1e-5 - 1) < 1e-5

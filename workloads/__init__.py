@@ -21,6 +21,7 @@ from .matrices import (
     instance_mix,
     rising_kappas,
     device_test_matrix,
+    paper_sweep_matrix,
 )
 
 __all__ = [
@@ -33,4 +34,5 @@ __all__ = [
     "instance_mix",
     "rising_kappas",
     "device_test_matrix",
+    "paper_sweep_matrix",
 ]

@@ -115,3 +115,21 @@ def device_test_matrix(m: int, n: int, kappa: float, seed: int, device="cuda"):
     a = torch.empty((n, m), device=device, dtype=torch.float64).t()  # column-major
     torch.mm(u, w, out=a)
     return a
+
+
+def paper_sweep_matrix(m: int, n: int, kappa: float, seed: int, order: str = "F") -> np.ndarray:
+    """The stability sweep's matrices: A = U diag(sigma) V^T with U (m x n),
+    V (n x n) the sign-fixed Q factors of matrices with entries uniform on
+    [-1, 1], and sigma_i = kappa^(1/2 - i/(n-1)) (so sigma_max = kappa^(1/2),
+    sigma_min = kappa^(-1/2), kappa_2 = kappa), as the paper builds them."""
+    rng = _rng(seed)
+    def q_of_uniform(r, c):
+        q, rr = np.linalg.qr(rng.uniform(-1.0, 1.0, (r, c)), mode="reduced")
+        d = np.sign(np.diag(rr))
+        d[d == 0] = 1.0
+        return q * d[None, :]
+    u = q_of_uniform(m, n)
+    v = q_of_uniform(n, n)
+    i = np.arange(n, dtype=np.float64)
+    sig = np.power(float(kappa), 0.5 - i / max(n - 1, 1))
+    return np.asarray((u * sig[None, :]) @ v.T, order=order)
