@@ -111,6 +111,18 @@ typedef struct mrcqr_info {
 
 typedef struct mrcqr_plan mrcqr_plan;
 
+/* Sketch transform flags (mrcqr_plan_create_ex, mrcqr_sketch_ex). Default
+ * (0): the DCT-II sketch, Y = gamma .* C fl_p(D A) with the sampled rows of
+ * the DCT-II, S drawn from [0, m), default s = 2n.
+ * MRCQR_SKETCH_RFFT: the paper's operator (Algorithm 2, FFT and Select):
+ * the real parts of c sampled bins of the m-point DFT of fl_p(D A),
+ * Y[i, :] = sqrt(c/m) sum_t cos(2 pi k_i t / m) fl_p(D A)[t, :], with S
+ * drawn from the floor(m/2) + 1 distinct bins {0, ..., floor(m/2)} (Hermitian
+ * symmetry), default c = 3n (the paper's default); c <= floor(m/2) + 1. Same
+ * precision rules as the DCT-II sketch (coefficients rounded to p, float32
+ * accumulation for p != FP64). */
+#define MRCQR_SKETCH_RFFT 1
+
 /* ---------------------------------------------------------------------
  * Whole factorization (Algorithm 2, all three stages).
  *
@@ -181,6 +193,11 @@ size_t mrcqr_factor_noalloc_max_workspace_bytes(void);
  * mrcqr_factor_batched on every device. No call of those may run
  * concurrently with it. Returns MRCQR_ERR_DEVICE if a HIP call failed. */
 int mrcqr_release_cache(void);
+
+/* mrcqr_plan_create with sketch transform flags (see MRCQR_SKETCH_RFFT); s =
+ * 0 takes the transform's default sketch size. Returns MRCQR_ERR_ARG for an
+ * unknown flag or a DFT sketch of more than floor(m/2) + 1 rows. */
+int mrcqr_plan_create_ex(int64_t m, int64_t n, int64_t s, int flags, mrcqr_plan** out);
 
 /* Plan API: a plan fixes (m, n, s); execute allocates nothing. Calls that
  * share a workspace must not overlap on the device (one stream, or events
@@ -274,6 +291,13 @@ int mrcqr_sketch(const double* A, int64_t m, int64_t n, int64_t lda,
                  const int32_t* S_dev, int64_t s, uint64_t seed, int precision,
                  double* Y, int64_t ldy, void* workspace, size_t workspace_bytes,
                  void* stream);
+/* The same with transform flags: MRCQR_SKETCH_RFFT takes the real parts of
+ * the DFT bins S_dev (values in [0, floor(m/2)], from mrcqr_draw with
+ * floor(m/2) + 1 in place of m) scaled by sqrt(s/m). */
+int mrcqr_sketch_ex(const double* A, int64_t m, int64_t n, int64_t lda,
+                    const int32_t* S_dev, int64_t s, uint64_t seed, int precision, int flags,
+                    double* Y, int64_t ldy, void* workspace, size_t workspace_bytes,
+                    void* stream);
 
 /* Stage 1 SketchQR: Householder thin QR of Y (s x n) in float32
  * (qr_precision = FP32) or float64 (FP64); Rs (n x n, upper, diag > 0,

@@ -126,3 +126,138 @@ def kappa_posterior(Rc: np.ndarray, X: np.ndarray) -> float:
     if not np.isfinite(k_ice) or not np.isfinite(k_pow):
         return float("inf")
     return max(k_ice, k_pow)
+
+
+# ---- the two other estimators the paper names (Section "Adaptive Precision
+# Selection"), kept for comparison with ICE ----------------------------------
+
+def _rademacher_column(seed: int, col: int, n: int) -> np.ndarray:
+    """+-1 entries from the counter-based generator (stream 3, one counter
+    per entry), for the estimator's random starting and replacement columns."""
+    from . import rng
+    return np.array([1.0 if (rng.h(seed, 3, col * n + i) >> 63) == 0 else -1.0 for i in range(n)])
+
+
+def onenorm_est(apply, apply_t, n: int, t: int = 2, itmax: int = 5, seed: int = 0) -> float:
+    """Block 1-norm estimate of ||B||_1 (Higham and Tisseur, "A block
+    algorithm for matrix 1-norm estimation", SIAM J. Matrix Anal. Appl. 21,
+    2000, Algorithm 2.4), B given by products apply(X) = B X and
+    apply_t(X) = B^T X with n x t blocks. A lower bound on ||B||_1.
+
+    Steps, as the algorithm states them: start from X with first column
+    ones/n and the others random +-1/n (parallel columns replaced); repeat
+    Y = B X, est = the largest column 1-norm of Y; stop when est stops
+    growing (keeping the previous one), after itmax steps, or when every
+    column of S = sign(Y) is parallel to one of the previous S; otherwise
+    replace columns of S parallel to another column of S or of the previous
+    S by random +-1 columns, form Z = B^T S, h_i = max_j |Z_ij|; stop if the
+    best index already gave the largest h (from the second step on); take
+    the t indices of largest h not used before as unit vectors for X (stop
+    if all of the t largest were used before)."""
+    if n == 1:
+        return float(abs(apply(np.ones((1, 1)))[0, 0]))
+    t = min(t, n)
+    rcol = [0]
+
+    def fresh():
+        c = _rademacher_column(seed, rcol[0], n)
+        rcol[0] += 1
+        return c
+
+    def parallel(a, b):
+        return abs(float(a @ b)) == n
+
+    X = np.ones((n, t))
+    for j in range(1, t):
+        c = fresh()
+        while any(parallel(c, X[:, i]) for i in range(j)):
+            c = fresh()
+        X[:, j] = c
+    X /= n
+    est_old = 0.0
+    S_old = np.zeros((n, t))
+    ind_hist = []
+    ind_best = 0
+    est = 0.0
+    for k in range(1, itmax + 2):
+        Y = apply(X)
+        norms = np.abs(Y).sum(axis=0)
+        est = float(norms.max())
+        if est > est_old or k == 2:
+            ind_best_col = int(np.argmax(norms))
+            if k >= 2:
+                ind_best = ind_cur[ind_best_col]
+        if k >= 2 and est <= est_old:
+            est = est_old
+            break
+        est_old = est
+        if k > itmax:
+            break
+        S = np.where(Y >= 0, 1.0, -1.0)
+        if k > 1 and all(any(parallel(S[:, j], S_old[:, i]) for i in range(t)) for j in range(t)):
+            break
+        for j in range(t):
+            while any(parallel(S[:, j], S[:, i]) for i in range(j)) or \
+                    (k > 1 and any(parallel(S[:, j], S_old[:, i]) for i in range(t))):
+                S[:, j] = fresh()
+        S_old = S.copy()
+        Z = apply_t(S)
+        h = np.abs(Z).max(axis=1)
+        if k >= 2 and h.max() == h[ind_best]:
+            break
+        order = np.argsort(-h, kind="stable")
+        if t > 1 and all(i in ind_hist for i in order[:t]):
+            break
+        ind_cur = [int(i) for i in order if i not in ind_hist][:t]
+        if len(ind_cur) < t:
+            break
+        X = np.zeros((n, t))
+        for j, i in enumerate(ind_cur):
+            X[i, j] = 1.0
+        ind_hist += ind_cur
+    return est
+
+
+def kappa_1norm_tri(R: np.ndarray, seed: int = 0) -> float:
+    """kappa_1(R) = ||R||_1 ||R^{-1}||_1 for upper-triangular R, the inverse's
+    norm estimated by onenorm_est with triangular solves."""
+    import scipy.linalg
+    R = np.triu(np.asarray(R, dtype=np.float64))
+    n = R.shape[0]
+    inv = onenorm_est(lambda X: scipy.linalg.solve_triangular(R, X, lower=False),
+                      lambda X: scipy.linalg.solve_triangular(R, X, lower=False, trans="T"), n, seed=seed)
+    return float(np.abs(R).sum(axis=0).max()) * inv
+
+
+def kappa_bound_gram(Rg: np.ndarray, seed: int = 0) -> float:
+    """The paper's classification bound kappa_2(A)^2 <= n ||A^T A||_1
+    ||(A^T A)^{-1}||_1, with A^T A = Rg^T Rg (its Cholesky factor) and the
+    inverse's norm estimated by onenorm_est; returns the square root."""
+    import scipy.linalg
+    Rg = np.triu(np.asarray(Rg, dtype=np.float64))
+    n = Rg.shape[0]
+    G = Rg.T @ Rg
+
+    def solve(X):
+        return scipy.linalg.solve_triangular(Rg, scipy.linalg.solve_triangular(Rg, X, lower=False, trans="T"),
+                                             lower=False)
+    inv = onenorm_est(solve, solve, n, seed=seed)
+    return float(np.sqrt(n * np.abs(G).sum(axis=0).max() * inv))
+
+
+def cholqr_probe(q: float, u: float = 2.0 ** -53) -> float:
+    """The CholQR probe's lower bound kappa_2(A) >= sqrt(q / (u (1 + q))),
+    q = ||I - Q^T Q||_2 of one CholQR (Algorithm 1) pass on A."""
+    return float(np.sqrt(q / (u * (1.0 + q))))
+
+
+def probe_kappa(A: np.ndarray) -> float:
+    """The CholQR probe on A: one pass of Algorithm 1, q from its Q, the
+    bound above; +inf when the pass breaks down (kappa(A) beyond about
+    u^(-1/2), the double regime)."""
+    from . import cholqr as CQ, metrics as MT
+    try:
+        Q, _ = CQ.cholqr(A)
+    except CQ.CholeskyBreakdown:
+        return float("inf")
+    return cholqr_probe(MT.orthogonality(Q))

@@ -52,11 +52,20 @@ class Result:
     intermediates: dict = field(default_factory=dict)
 
 
-def stage1(A: np.ndarray, prec: int, seed: int, s: int):
+DCT, RFFT = "dct", "rfft"
+
+
+def stage1(A: np.ndarray, prec: int, seed: int, s: int, transform: str = DCT):
+    """Draw, sketch (DCT-II rows, or the paper's real DFT bins from
+    {0..m/2}), QR of the sketch in the precision the paper fixes."""
     m, n = A.shape
-    S = rng.sample_rows(seed, m, s)
     d = rng.signs(seed, m)
-    Y = SK.sketch(A, S, d, prec)
+    if transform == RFFT:
+        S = rng.sample_rows(seed, m // 2 + 1, s)
+        Y = SK.sketch_rfft(A, S, d, prec)
+    else:
+        S = rng.sample_rows(seed, m, s)
+        Y = SK.sketch(A, S, d, prec)
     qr_dtype = np.float64 if prec == P.FP64 else np.float32
     Rs = HH.householder_r(Y, dtype=qr_dtype).astype(np.float64)
     return S, d, Y, Rs
@@ -81,12 +90,12 @@ def _rs_ok(Rs: np.ndarray) -> bool:
 
 
 def factor(A: np.ndarray, precision: int, seed: int, s: int | None = None,
-           start: int = P.FP16, keep: bool = False) -> Result:
+           start: int = P.FP16, keep: bool = False, transform: str = DCT) -> Result:
     A = np.asarray(A, dtype=np.float64)
     m, n = A.shape
-    s = 2 * n if s is None else s
+    s = (3 * n if transform == RFFT else 2 * n) if s is None else s
     if precision != AUTO:
-        S, d, Y, Rs = stage1(A, precision, seed, s)
+        S, d, Y, Rs = stage1(A, precision, seed, s, transform)
         krs = CE.kappa_est(Rs) if _rs_ok(Rs) else float("inf")
         inter = {"S": S, "d": d, "Y": Y, "Rs": Rs} if keep else {}
         if not _rs_ok(Rs):
@@ -105,7 +114,7 @@ def factor(A: np.ndarray, precision: int, seed: int, s: int | None = None,
     escalations = 0
     while True:
         prec = LADDER[level]
-        S, d, Y, Rs = stage1(A, prec, seed, s)
+        S, d, Y, Rs = stage1(A, prec, seed, s, transform)
         ok = _rs_ok(Rs)
         krs = CE.kappa_est(Rs) if ok else float("inf")
         if (not ok or krs >= TAU[prec]) and level + 1 < len(LADDER):

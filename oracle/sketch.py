@@ -39,6 +39,19 @@ def coefficients(k: np.ndarray, t: np.ndarray, m: int) -> np.ndarray:
     return np.cos(np.pi * phase(k, t, m).astype(np.float64) / (2.0 * m))
 
 
+def rfft_phase(k: np.ndarray, t: np.ndarray, m: int) -> np.ndarray:
+    """4 k t mod 4m: the phase of cos(2 pi k t / m) = cos(pi * phase / (2m)),
+    exact in int64."""
+    k = np.asarray(k, dtype=np.int64)
+    t = np.asarray(t, dtype=np.int64)
+    return ((4 * t[None, :]) % (4 * m) * k[:, None]) % (4 * m)
+
+
+def rfft_coefficients(k: np.ndarray, t: np.ndarray, m: int) -> np.ndarray:
+    """Re exp(-2 pi i k t / m) = cos(2 pi k t / m) in float64."""
+    return np.cos(np.pi * rfft_phase(k, t, m).astype(np.float64) / (2.0 * m))
+
+
 def gammas(S: np.ndarray, s: int) -> np.ndarray:
     S = np.asarray(S)
     return np.where(S == 0, np.sqrt(1.0 / s), np.sqrt(2.0 / s))
@@ -86,3 +99,44 @@ def sketch_abs_bound(A: np.ndarray, S: np.ndarray, d: np.ndarray, prec: int, chu
         t = np.arange(t0, min(m, t0 + chunk), dtype=np.int64)
         y += np.abs(coefficients(S, t, m)) @ at[t0:t0 + t.shape[0]]
     return y * gammas(S, S.shape[0] if s_total is None else s_total)[:, None]
+
+
+def sketch_rfft(A: np.ndarray, S: np.ndarray, d: np.ndarray, prec: int, chunk: int = 1 << 15,
+                s_total: int | None = None) -> np.ndarray:
+    """The paper's operator (Algorithm 2, FFT and Select): the real parts of
+    the DFT bins S (0 <= k <= m/2) of fl_p(D A), scaled by sqrt(c/m):
+      Y[i, j] = sqrt(c/m) * sum_t cos(2 pi k_i t / m) * at[t, j].
+    Precision rules as in sketch(): coefficients and data rounded to p, the
+    products summed exactly here (float32 on the GPU), the scale applied
+    after the sum, Y rounded to float32 for p != FP64."""
+    A = np.asarray(A, dtype=np.float64)
+    m, n = A.shape
+    S = np.asarray(S, dtype=np.int64)
+    c_total = S.shape[0] if s_total is None else s_total
+    at = signed_cast(A, d, prec)
+    y = np.zeros((S.shape[0], n), dtype=np.float64)
+    for t0 in range(0, m, chunk):
+        t = np.arange(t0, min(m, t0 + chunk), dtype=np.int64)
+        c = rfft_coefficients(S, t, m)
+        if prec != P.FP64:
+            c = P.round_to(c, prec)
+        y += c @ at[t0:t0 + t.shape[0]]
+    y *= np.sqrt(c_total / m)
+    if prec != P.FP64:
+        y = P.to_f32(y)
+    return y
+
+
+def sketch_rfft_abs_bound(A: np.ndarray, S: np.ndarray, d: np.ndarray, prec: int, chunk: int = 1 << 15,
+                          s_total: int | None = None) -> np.ndarray:
+    """sqrt(c/m) sum_t |cos(2 pi k t / m)| |at[t, j]|, the error scale of
+    sketch_rfft (elementwise)."""
+    A = np.asarray(A, dtype=np.float64)
+    m, n = A.shape
+    S = np.asarray(S, dtype=np.int64)
+    at = np.abs(signed_cast(A, d, prec))
+    y = np.zeros((S.shape[0], n), dtype=np.float64)
+    for t0 in range(0, m, chunk):
+        t = np.arange(t0, min(m, t0 + chunk), dtype=np.int64)
+        y += np.abs(rfft_coefficients(S, t, m)) @ at[t0:t0 + t.shape[0]]
+    return y * np.sqrt((S.shape[0] if s_total is None else s_total) / m)

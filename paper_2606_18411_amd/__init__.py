@@ -29,6 +29,7 @@ STATUS = {
     0: "ok", 1: "invalid argument", 2: "non-finite sketch", 3: "cholesky breakdown",
     4: "sketch singular", 5: "workspace", 6: "device error", 7: "posterior warning", 8: "unsupported",
 }
+TRANSFORM = {"dct": 0, "rfft": 1}  # sketch transform: DCT-II rows, or the paper's real DFT bins
 OK, ERR_ARG, ERR_NONFINITE, ERR_CHOL, ERR_SINGULAR, ERR_WORKSPACE, ERR_DEVICE, WARN_POSTERIOR, ERR_UNSUPPORTED = range(9)
 
 _lib = None
@@ -51,6 +52,8 @@ def lib() -> ctypes.CDLL:
         sig = {
             "mrcqr_factor": (i32, [vp, i64, i64, i64, i32, u64, i64, vp, i64, vp, i64, vp, vp]),
             "mrcqr_plan_create": (i32, [i64, i64, i64, ctypes.POINTER(vp)]),
+            "mrcqr_plan_create_ex": (i32, [i64, i64, i64, i32, ctypes.POINTER(vp)]),
+            "mrcqr_sketch_ex": (i32, [vp, i64, i64, i64, vp, i64, u64, i32, i32, vp, i64, vp, sz, vp]),
             "mrcqr_plan_workspace_bytes": (sz, [vp]),
             "mrcqr_execute": (i32, [vp, vp, sz, vp, i64, i32, u64, vp, i64, vp, i64, vp, vp]),
             "mrcqr_plan_destroy": (i32, [vp]),
@@ -228,11 +231,15 @@ def cholqr2(A: torch.Tensor, stream=None, sync: bool = True):
 
 
 class Plan:
-    """A plan for fixed (m, n, s) with its own workspace; execute() allocates nothing."""
+    """A plan for fixed (m, n, s) with its own workspace; execute() allocates nothing.
+    transform: "dct" (DCT-II rows, default s = 2n) or "rfft" (the paper's real
+    DFT bins, default s = 3n)."""
 
-    def __init__(self, m: int, n: int, s: int | None = None, device="cuda"):
+    def __init__(self, m: int, n: int, s: int | None = None, device="cuda", transform: str = "dct"):
         p = ctypes.c_void_p()
-        _check(lib().mrcqr_plan_create(m, n, s or 0, ctypes.byref(p)), "mrcqr_plan_create")
+        _check(lib().mrcqr_plan_create_ex(m, n, s or 0, TRANSFORM[transform], ctypes.byref(p)),
+               "mrcqr_plan_create_ex")
+        self.transform = transform
         self._p = p
         self.m, self.n = m, n
         self.workspace_bytes = int(lib().mrcqr_plan_workspace_bytes(p))
@@ -371,21 +378,24 @@ def draw(seed: int, m: int, s: int, signs: bool = False, device="cuda", stream=N
     return (S, D) if signs else S
 
 
-def sketch(A: torch.Tensor, S: torch.Tensor, seed: int, precision="fp16", stream=None) -> torch.Tensor:
+def sketch(A: torch.Tensor, S: torch.Tensor, seed: int, precision="fp16", stream=None,
+           transform: str = "dct") -> torch.Tensor:
     m, n = A.shape
     _mat(A, m, n, "A")
     if not (isinstance(S, torch.Tensor) and S.dim() == 1 and S.dtype == torch.int32):
         raise TypeError("S must be a 1-D int32 tensor")
     s = S.shape[0]
     _same_cuda_device([("A", A), ("S", S)])
-    if s < 1 or s > m or int(S.min()) < 0 or int(S.max()) >= m:
-        raise ValueError(f"S must hold 1..m indices in [0, {m})")
+    kmax = m // 2 + 1 if transform == "rfft" else m
+    if s < 1 or s > kmax or int(S.min()) < 0 or int(S.max()) >= kmax:
+        raise ValueError(f"S must hold 1..{kmax} indices in [0, {kmax})")
     Y = empty_colmajor(s, n, A.device)
     p = _prec(precision)
     wsb = int(lib().mrcqr_sketch_workspace_bytes(m, n, s, p))
     ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=A.device)
-    _check(lib().mrcqr_sketch(A.data_ptr(), m, n, _ld(A), S.data_ptr(), s, seed & (2 ** 64 - 1), p, Y.data_ptr(),
-                              _ld(Y), ws.data_ptr(), wsb, _stream(stream)), "mrcqr_sketch")
+    _check(lib().mrcqr_sketch_ex(A.data_ptr(), m, n, _ld(A), S.data_ptr(), s, seed & (2 ** 64 - 1), p,
+                                 TRANSFORM[transform], Y.data_ptr(), _ld(Y), ws.data_ptr(), wsb, _stream(stream)),
+           "mrcqr_sketch_ex")
     return Y
 
 

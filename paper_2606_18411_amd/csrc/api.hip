@@ -17,7 +17,7 @@ hipError_t launch_draw(uint64_t seed, int m, int s, int32_t* S, int8_t* D, hipSt
                        int prec = 0, int auto_mode = 0);
 hipError_t launch_sketch(int prec, const double* A, int64_t lda, int m, int n, const int32_t* S, int s,
                          uint64_t seed, void* Ypart, double* Y, int64_t ldy, const Ctrl* ctrl, int phase,
-                         hipStream_t st);
+                         hipStream_t st, int xform);
 size_t sketch_partial_bytes(int64_t m, int64_t n, int64_t s, int prec);
 hipError_t launch_sketch_qr(bool f64, const double* Y, int s, int n, int64_t ldy, double* Rs, int64_t ldr,
                             double* kappa, Ctrl* ctrl, int slot, int phase, hipStream_t st);
@@ -106,6 +106,7 @@ int hip_status(hipError_t e) { return e == hipSuccess ? MRCQR_OK : MRCQR_ERR_DEV
 
 struct mrcqr_plan {
   int64_t m, n, s;
+  int xform = 0;  // 0: DCT-II sketch; 1: real part of the DFT (MRCQR_SKETCH_RFFT)
   size_t off_ctrl, off_S, off_Ypart, off_Y, off_Rs, off_Gpart, off_G, off_Rc, off_Rci, off_Tw, off_B, total;
 };
 
@@ -145,13 +146,15 @@ static int execute(const mrcqr_plan* p, char* ws, const double* A, int64_t lda, 
   hipError_t e;
   const bool automode = prec == MRCQR_PREC_AUTO || prec == MRCQR_PREC_AUTO_CARRY;
   const int amode = prec == MRCQR_PREC_AUTO_CARRY ? AM_CARRY : automode ? AM_AUTO : AM_FIXED;
-  if ((e = launch_draw(seed, m, s, S, nullptr, st, ctrl, automode ? P_FP16 : prec, amode)) != hipSuccess)
+  // the DFT variant samples the floor(m/2) + 1 distinct bins of a real signal
+  const int mdraw = p->xform ? m / 2 + 1 : m;
+  if ((e = launch_draw(seed, mdraw, s, S, nullptr, st, ctrl, automode ? P_FP16 : prec, amode)) != hipSuccess)
     return MRCQR_ERR_DEVICE;
   // The launch sequence is static: in AUTO every attempt is enqueued and
   // the kernels of an attempt whose precision is not the current one (or of
   // a rerun that was not requested) return immediately.
   auto stage1 = [&](int pp, int phase) -> bool {
-    return launch_sketch(pp, A, lda, m, n, S, s, seed, Ypart, Y, s, ctrl, phase, st) == hipSuccess &&
+    return launch_sketch(pp, A, lda, m, n, S, s, seed, Ypart, Y, s, ctrl, phase, st, p->xform) == hipSuccess &&
            launch_sketch_qr(pp == P_FP64, Y, s, n, s, Rs, n, nullptr, ctrl, pp, phase, st) == hipSuccess;
   };
   // Stage 2 and 3 of one pass; Q is formed in the pass's tail phase, which
@@ -391,16 +394,23 @@ bool stream_capturing(hipStream_t st) {
 
 extern "C" {
 
-int mrcqr_plan_create(int64_t m, int64_t n, int64_t s, mrcqr_plan** out) {
-  if (!out) return MRCQR_ERR_ARG;
-  if (s == 0) s = 2 * n;
+int mrcqr_plan_create_ex(int64_t m, int64_t n, int64_t s, int flags, mrcqr_plan** out) {
+  if (!out || (flags & ~MRCQR_SKETCH_RFFT) != 0) return MRCQR_ERR_ARG;
+  const bool rfft = (flags & MRCQR_SKETCH_RFFT) != 0;
+  if (s == 0) s = rfft ? 3 * n : 2 * n;
   const int c = check_shape(m, n, s);
   if (c) return c;
+  if (rfft && s > m / 2 + 1) return MRCQR_ERR_ARG;  // distinct bins of a real signal
   mrcqr_plan* p = new mrcqr_plan();
   p->m = m; p->n = n; p->s = s;
+  p->xform = rfft ? 1 : 0;
   plan_layout(p);
   *out = p;
   return MRCQR_OK;
+}
+
+int mrcqr_plan_create(int64_t m, int64_t n, int64_t s, mrcqr_plan** out) {
+  return mrcqr_plan_create_ex(m, n, s, 0, out);
 }
 
 size_t mrcqr_plan_workspace_bytes(const mrcqr_plan* plan) { return plan ? plan->total : 0; }
@@ -619,12 +629,20 @@ size_t mrcqr_sketch_workspace_bytes(int64_t m, int64_t n, int64_t s, int precisi
 int mrcqr_sketch(const double* A, int64_t m, int64_t n, int64_t lda, const int32_t* S_dev, int64_t s,
                  uint64_t seed, int precision, double* Y, int64_t ldy, void* workspace, size_t workspace_bytes,
                  void* stream) {
+  return mrcqr_sketch_ex(A, m, n, lda, S_dev, s, seed, precision, 0, Y, ldy, workspace, workspace_bytes, stream);
+}
+
+int mrcqr_sketch_ex(const double* A, int64_t m, int64_t n, int64_t lda, const int32_t* S_dev, int64_t s,
+                    uint64_t seed, int precision, int flags, double* Y, int64_t ldy, void* workspace,
+                    size_t workspace_bytes, void* stream) {
   if (!A || !S_dev || !Y || !valid_prec(precision, false)) return MRCQR_ERR_ARG;
+  if ((flags & ~MRCQR_SKETCH_RFFT) != 0) return MRCQR_ERR_ARG;
+  if ((flags & MRCQR_SKETCH_RFFT) && s > m / 2 + 1) return MRCQR_ERR_ARG;
   if (n < 1 || m < 1 || s < 1 || s > m || lda < m || ldy < s) return MRCQR_ERR_ARG;
   if (m >= MMAX || s > SMAX) return MRCQR_ERR_UNSUPPORTED;
   if (!workspace || workspace_bytes < mrcqr_sketch_workspace_bytes(m, n, s, precision)) return MRCQR_ERR_WORKSPACE;
   return hip_status(launch_sketch(precision, A, lda, (int)m, (int)n, S_dev, (int)s, seed, workspace, Y, ldy,
-                                  nullptr, PH_FIRST, as_stream(stream)));
+                                  nullptr, PH_FIRST, as_stream(stream), (flags & MRCQR_SKETCH_RFFT) ? 1 : 0));
 }
 
 int mrcqr_sketch_qr(const double* Y, int64_t s, int64_t n, int64_t ldy, int qr_precision, double* Rs,

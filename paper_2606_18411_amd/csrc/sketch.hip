@@ -1,7 +1,12 @@
-// Algorithm 2, Stage 1: DiagMult (sign flip + cast to p), the DCT-II
-// transform along the rows, and Select (the s sampled rows), computed as one
-// dense contraction Y = C_S * fl_p(D A) on the matrix cores, where
-// C_S[i, t] = cos(pi (2t+1) S[i] / (2m)) are generated on the fly.
+// Algorithm 2, Stage 1: DiagMult (sign flip + cast to p), the transform
+// along the rows, and Select (the s sampled rows), computed as one dense
+// contraction Y = C_S * fl_p(D A) on the matrix cores, with the rows C_S of
+// the transform generated on the fly:
+//   DCT-II (default):  C_S[i, t] = cos(pi (2t+1) k / (2m)),  k = S[i] < m;
+//   real part of the DFT (the paper's operator, Algorithm 2 FFT + Select):
+//                      C_S[i, t] = cos(2 pi k t / m),       k = S[i] <= m/2.
+// Both are cos((pi/2) phi / m) of an integer phase phi = (a t + b) k mod 4m,
+// (a, b) = (2, 1) and (4, 0).
 //
 // Work decomposition: grid (row chunks, column blocks of 128, sketch-row
 // blocks of 256). A workgroup of 8 waves (for n <= 16, 32, 64: 1, 2, 4
@@ -68,8 +73,8 @@ __device__ __forceinline__ void phase_sincos(uint32_t phi, uint32_t m, F inv_m, 
   sn = (q == 0) ? sa : (q == 1) ? ca : (q == 2) ? -sa : -ca;
 }
 
-__device__ __forceinline__ uint32_t phase_of(uint64_t t, uint64_t k, uint64_t m4) {
-  return (uint32_t)(((2 * t + 1) * k) % m4);
+__device__ __forceinline__ uint32_t phase_of(uint64_t t, uint64_t k, uint64_t m4, uint64_t pa, uint64_t pb) {
+  return (uint32_t)(((pa * t + pb) * k) % m4);
 }
 __device__ __forceinline__ uint32_t add_mod(uint32_t a, uint32_t b, uint32_t m4) {
   uint32_t c = a + b;
@@ -108,7 +113,7 @@ __device__ __forceinline__ void sketch_body(
     const double* __restrict__ A, int64_t lda, int m, int n,
     const int32_t* __restrict__ S, int s, uint64_t seed, int rows_per_chunk,
     typename SkT<P>::acc* __restrict__ Ypart, const Ctrl* __restrict__ ctrl, int phase,
-    int chunk, int cblk, int sblk) {
+    int chunk, int cblk, int sblk, int xform) {
   using T = SkT<P>;
   using elem = typename T::elem;
   using acc_t = typename T::acc;
@@ -144,6 +149,7 @@ __device__ __forceinline__ void sketch_body(
   const int npanels = (int)((tend - tstart + SK_PANEL - 1) / SK_PANEL);
   const uint32_t um = (uint32_t)m, m4 = 4u * (uint32_t)m;
   const uint64_t key0 = stream_key(seed, 0);
+  const uint64_t pa = xform ? 4 : 2, pb = xform ? 0 : 1;  // phase (pa t + pb) k
 
   // ---- this lane's two sketch rows (one per M tile) and their phases ----
   // phi[mt]: exact phase (2t+1)k mod 4m at the lane's first row of the
@@ -164,14 +170,14 @@ __device__ __forceinline__ void sketch_body(
     kvalid[mt] = row < s;
     const uint32_t k = kvalid[mt] ? (uint32_t)S[row] : 0u;
     const uint64_t tl = (uint64_t)tstart + (KSTEP == 32 ? 8 * g : g);
-    phi[mt] = phase_of(tl, k, m4);
-    inc_p[mt] = (uint32_t)((2ull * SK_PANEL * k) % m4);
+    phi[mt] = phase_of(tl, k, m4, pa, pb);
+    inc_p[mt] = (uint32_t)((pa * SK_PANEL * k) % m4);
     // the lane steps 1 row (K=32: 8 consecutive rows) or 4 rows (K=4) at a time
-    const uint32_t step = (uint32_t)((2ull * (KSTEP == 32 ? 1 : 4) * k) % m4);
+    const uint32_t step = (uint32_t)((pa * (KSTEP == 32 ? 1 : 4) * k) % m4);
     double c, sn;
     phase_sincos<double>(step, um, inv_md, c, sn); c1[mt] = (rot_t)c; s1[mt] = (rot_t)sn;
     tc1[mt] = (float)(2.0 * c);
-    phase_sincos<double>((uint32_t)((64ull * k) % m4), um, inv_md, c, sn); cK[mt] = (rot_t)c; sK[mt] = (rot_t)sn;
+    phase_sincos<double>((uint32_t)((pa * 32 * k) % m4), um, inv_md, c, sn); cK[mt] = (rot_t)c; sK[mt] = (rot_t)sn;
     phase_sincos<double>(inc_p[mt], um, inv_md, c, sn); cP[mt] = (rot_t)c; sP[mt] = (rot_t)sn;
     phase_sincos<double>(phi[mt], um, inv_md, c, sn); cb[mt] = (rot_t)c; sb[mt] = (rot_t)sn;
   }
@@ -391,9 +397,9 @@ template <int P, int NTL, bool FULL>
 __global__ __launch_bounds__(64 * NTL) void sketch_kernel(
     const double* __restrict__ A, int64_t lda, int m, int n,
     const int32_t* __restrict__ S, int s, uint64_t seed, int rows_per_chunk,
-    typename SkT<P>::acc* __restrict__ Ypart, const Ctrl* __restrict__ ctrl, int phase) {
+    typename SkT<P>::acc* __restrict__ Ypart, const Ctrl* __restrict__ ctrl, int phase, int xform) {
   sketch_body<P, NTL, FULL>(A, lda, m, n, S, s, seed, rows_per_chunk, Ypart, ctrl, phase, blockIdx.x, blockIdx.y,
-                            blockIdx.z);
+                            blockIdx.z, xform);
 }
 
 // Grouped (members with n <= 128 and s <= 256: one column block and one
@@ -409,18 +415,21 @@ __global__ __launch_bounds__(64 * NTL) void sketch_grouped(const BatchInst* __re
   if ((int)blockIdx.x >= d.sk_chunks) return;
   sketch_body<P, NTL, FULL>(call.A[i], call.lda[i], d.m, d.n, bat_ptr<int32_t>(call, d, d.off_S), d.s, call.seed[i],
                        d.sk_rows, bat_ptr<typename SkT<P>::acc>(call, d, d.off_Ypart),
-                       bat_ptr<Ctrl>(call, d, d.off_ctrl), phase, blockIdx.x, 0, 0);
+                       bat_ptr<Ctrl>(call, d, d.off_ctrl), phase, blockIdx.x, 0, 0, 0);
 }
 
-// Y[srow, col] = gamma_k * sum over chunks (float64, fixed order), then
-// rounded to float32 for the low-precision sketches. A block covers 64
+// Y[srow, col] = scale * sum over chunks (float64, fixed order), then
+// rounded to float32 for the low-precision sketches (flags bit 0); scale =
+// gamma_k = sqrt(1/s) (k = 0) or sqrt(2/s) for the DCT-II, sqrt(s/m) for
+// the real part of the DFT (flags bit 1; the paper's sqrt(c/m)). A block covers 64
 // consecutive (col, srow) entries; its 4 waves sum 4 contiguous chunk
 // ranges, combined in LDS in fixed order.
 template <typename AccT>
 __device__ __forceinline__ void sketch_reduce_body(const AccT* __restrict__ Ypart, int chunks, int n, int s,
                                      const int32_t* __restrict__ S, double* __restrict__ Y, int64_t ldy,
-                                     int round_f32, const Ctrl* __restrict__ ctrl, int slot, int phase) {
+                                     int flags, int m, const Ctrl* __restrict__ ctrl, int slot, int phase) {
   if (skip_launch(ctrl, slot, phase)) return;
+  const int round_f32 = flags & 1;
   __shared__ double part[4][64];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int64_t idx = (int64_t)blockIdx.x * 64 + l;
@@ -445,7 +454,8 @@ __device__ __forceinline__ void sketch_reduce_body(const AccT* __restrict__ Ypar
   if (w == 0 && idx < tot) {
     const int col = (int)(idx / s), srow = (int)(idx % s);
     const double sum = ((part[0][l] + part[1][l]) + part[2][l]) + part[3][l];
-    const double gamma = (S[srow] == 0) ? sqrt(1.0 / (double)s) : sqrt(2.0 / (double)s);
+    const double gamma = (flags & 2) ? sqrt((double)s / (double)m)
+                                     : ((S[srow] == 0) ? sqrt(1.0 / (double)s) : sqrt(2.0 / (double)s));
     double y = gamma * sum;
     if (round_f32) y = (double)(float)y;
     Y[srow + (int64_t)col * ldy] = y;
@@ -455,8 +465,8 @@ __device__ __forceinline__ void sketch_reduce_body(const AccT* __restrict__ Ypar
 template <typename AccT>
 __global__ __launch_bounds__(256) void sketch_reduce_kernel(const AccT* __restrict__ Ypart, int chunks, int n, int s,
                                      const int32_t* __restrict__ S, double* __restrict__ Y, int64_t ldy,
-                                     int round_f32, const Ctrl* __restrict__ ctrl, int slot, int phase) {
-  sketch_reduce_body<AccT>(Ypart, chunks, n, s, S, Y, ldy, round_f32, ctrl, slot, phase);
+                                     int flags, int m, const Ctrl* __restrict__ ctrl, int slot, int phase) {
+  sketch_reduce_body<AccT>(Ypart, chunks, n, s, S, Y, ldy, flags, m, ctrl, slot, phase);
 }
 
 template <typename AccT>
@@ -467,7 +477,7 @@ __global__ __launch_bounds__(256) void sketch_reduce_grouped(const BatchInst* __
   const BatchInst& d = bi[i];
   if ((int64_t)blockIdx.x * 64 >= (int64_t)d.n * d.s) return;
   sketch_reduce_body<AccT>(bat_ptr<const AccT>(call, d, d.off_Ypart), d.sk_chunks, d.n, d.s,
-                           bat_ptr<const int32_t>(call, d, d.off_S), bat_ptr<double>(call, d, d.off_Y), d.s, round_f32,
+                           bat_ptr<const int32_t>(call, d, d.off_S), bat_ptr<double>(call, d, d.off_Y), d.s, round_f32, d.m,
                            bat_ptr<const Ctrl>(call, d, d.off_ctrl), slot, phase);
 }
 
@@ -491,14 +501,14 @@ static int sketch_waves(int v) { return v == 0 ? 1 : v == 1 ? 2 : v == 2 ? 4 : 8
 template <int P>
 static void launch_sketch_v(int v, dim3 grid, hipStream_t st, const double* A, int64_t lda, int m, int n,
                             const int32_t* S, int s, uint64_t seed, int rows_per_chunk, typename SkT<P>::acc* Ypart,
-                            const Ctrl* ctrl, int phase) {
+                            const Ctrl* ctrl, int phase, int xform) {
   const dim3 block(64 * sketch_waves(v));
   switch (v) {
-    case 0: hipLaunchKernelGGL((sketch_kernel<P, 1, false>), grid, block, 0, st, A, lda, m, n, S, s, seed, rows_per_chunk, Ypart, ctrl, phase); break;
-    case 1: hipLaunchKernelGGL((sketch_kernel<P, 2, false>), grid, block, 0, st, A, lda, m, n, S, s, seed, rows_per_chunk, Ypart, ctrl, phase); break;
-    case 2: hipLaunchKernelGGL((sketch_kernel<P, 4, false>), grid, block, 0, st, A, lda, m, n, S, s, seed, rows_per_chunk, Ypart, ctrl, phase); break;
-    case 3: hipLaunchKernelGGL((sketch_kernel<P, 8, false>), grid, block, 0, st, A, lda, m, n, S, s, seed, rows_per_chunk, Ypart, ctrl, phase); break;
-    default: hipLaunchKernelGGL((sketch_kernel<P, 8, true>), grid, block, 0, st, A, lda, m, n, S, s, seed, rows_per_chunk, Ypart, ctrl, phase); break;
+    case 0: hipLaunchKernelGGL((sketch_kernel<P, 1, false>), grid, block, 0, st, A, lda, m, n, S, s, seed, rows_per_chunk, Ypart, ctrl, phase, xform); break;
+    case 1: hipLaunchKernelGGL((sketch_kernel<P, 2, false>), grid, block, 0, st, A, lda, m, n, S, s, seed, rows_per_chunk, Ypart, ctrl, phase, xform); break;
+    case 2: hipLaunchKernelGGL((sketch_kernel<P, 4, false>), grid, block, 0, st, A, lda, m, n, S, s, seed, rows_per_chunk, Ypart, ctrl, phase, xform); break;
+    case 3: hipLaunchKernelGGL((sketch_kernel<P, 8, false>), grid, block, 0, st, A, lda, m, n, S, s, seed, rows_per_chunk, Ypart, ctrl, phase, xform); break;
+    default: hipLaunchKernelGGL((sketch_kernel<P, 8, true>), grid, block, 0, st, A, lda, m, n, S, s, seed, rows_per_chunk, Ypart, ctrl, phase, xform); break;
   }
 }
 
@@ -533,7 +543,8 @@ size_t sketch_partial_bytes(int64_t m, int64_t n, int64_t s, int prec) {
 
 hipError_t launch_sketch(int prec, const double* A, int64_t lda, int m, int n, const int32_t* S, int s,
                          uint64_t seed, void* Ypart, double* Y, int64_t ldy, const Ctrl* ctrl, int phase,
-                         hipStream_t st) {
+                         hipStream_t st, int xform) {
+  const int fl = 1 | (xform ? 2 : 0), fl64 = xform ? 2 : 0;
   SketchGeom gg = sketch_geometry(m);
   const int v = sketch_variant(n, s);
   const int srows = 32 * sketch_waves(v);  // sketch rows per block
@@ -543,20 +554,20 @@ hipError_t launch_sketch(int prec, const double* A, int64_t lda, int m, int n, c
   dim3 rgrid((unsigned)((tot + 63) / 64));
   switch (prec) {
     case P_FP16:
-      launch_sketch_v<P_FP16>(v, grid, st, A, lda, m, n, S, s, seed, gg.rows_per_chunk, (float*)Ypart, ctrl, phase);
-      hipLaunchKernelGGL(sketch_reduce_kernel<float>, rgrid, dim3(rb), 0, st, (const float*)Ypart, gg.chunks, n, s, S, Y, ldy, 1, ctrl, (int)P_FP16, phase);
+      launch_sketch_v<P_FP16>(v, grid, st, A, lda, m, n, S, s, seed, gg.rows_per_chunk, (float*)Ypart, ctrl, phase, xform);
+      hipLaunchKernelGGL(sketch_reduce_kernel<float>, rgrid, dim3(rb), 0, st, (const float*)Ypart, gg.chunks, n, s, S, Y, ldy, fl, m, ctrl, (int)P_FP16, phase);
       break;
     case P_BF16:
-      launch_sketch_v<P_BF16>(v, grid, st, A, lda, m, n, S, s, seed, gg.rows_per_chunk, (float*)Ypart, ctrl, phase);
-      hipLaunchKernelGGL(sketch_reduce_kernel<float>, rgrid, dim3(rb), 0, st, (const float*)Ypart, gg.chunks, n, s, S, Y, ldy, 1, ctrl, (int)P_BF16, phase);
+      launch_sketch_v<P_BF16>(v, grid, st, A, lda, m, n, S, s, seed, gg.rows_per_chunk, (float*)Ypart, ctrl, phase, xform);
+      hipLaunchKernelGGL(sketch_reduce_kernel<float>, rgrid, dim3(rb), 0, st, (const float*)Ypart, gg.chunks, n, s, S, Y, ldy, fl, m, ctrl, (int)P_BF16, phase);
       break;
     case P_FP32:
-      launch_sketch_v<P_FP32>(v, grid, st, A, lda, m, n, S, s, seed, gg.rows_per_chunk, (float*)Ypart, ctrl, phase);
-      hipLaunchKernelGGL(sketch_reduce_kernel<float>, rgrid, dim3(rb), 0, st, (const float*)Ypart, gg.chunks, n, s, S, Y, ldy, 1, ctrl, (int)P_FP32, phase);
+      launch_sketch_v<P_FP32>(v, grid, st, A, lda, m, n, S, s, seed, gg.rows_per_chunk, (float*)Ypart, ctrl, phase, xform);
+      hipLaunchKernelGGL(sketch_reduce_kernel<float>, rgrid, dim3(rb), 0, st, (const float*)Ypart, gg.chunks, n, s, S, Y, ldy, fl, m, ctrl, (int)P_FP32, phase);
       break;
     case P_FP64:
-      launch_sketch_v<P_FP64>(v, grid, st, A, lda, m, n, S, s, seed, gg.rows_per_chunk, (double*)Ypart, ctrl, phase);
-      hipLaunchKernelGGL(sketch_reduce_kernel<double>, rgrid, dim3(rb), 0, st, (const double*)Ypart, gg.chunks, n, s, S, Y, ldy, 0, ctrl, (int)P_FP64, phase);
+      launch_sketch_v<P_FP64>(v, grid, st, A, lda, m, n, S, s, seed, gg.rows_per_chunk, (double*)Ypart, ctrl, phase, xform);
+      hipLaunchKernelGGL(sketch_reduce_kernel<double>, rgrid, dim3(rb), 0, st, (const double*)Ypart, gg.chunks, n, s, S, Y, ldy, fl64, m, ctrl, (int)P_FP64, phase);
       break;
     default:
       return hipErrorInvalidValue;

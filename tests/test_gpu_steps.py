@@ -51,6 +51,25 @@ def test_sketch_matches_definition(M, prec, m, n, s, kind):
         assert np.array_equal(Y, Y.astype(np.float32).astype(np.float64))  # float32 values
 
 
+@pytest.mark.parametrize("prec", [P.FP64, P.FP32, P.FP16, P.BF16])
+@pytest.mark.parametrize("m,n,c", [(4096, 32, 96), (5003, 20, 60), (70001, 128, 384), (1 << 20, 64, 192),
+                                   (401, 50, 150)])
+def test_rfft_sketch_matches_definition(M, prec, m, n, c):
+    """The paper's operator (real parts of DFT bins from {0..m/2}, scale
+    sqrt(c/m)) on the same MFMA contraction, element by element."""
+    progress(f"rfft sketch {NAMES[prec]} m={m} n={n} c={c}")
+    seed = 77 + m
+    A = W.test_matrix(m, n, 1e4, 5)
+    S = rng.sample_rows(seed, m // 2 + 1, c)
+    assert np.array_equal(to_host(M.draw(seed, m // 2 + 1, c)).astype(np.int64), S)
+    d = rng.signs(seed, m)
+    Y = to_host(M.sketch(to_dev(A), torch.from_numpy(S.astype(np.int32)).cuda(), seed, NAMES[prec], transform="rfft"))
+    Yo = SK.sketch_rfft(A, S, d, prec)
+    bound = SK.sketch_rfft_abs_bound(A, S, d, prec)
+    err = np.abs(Y - Yo) - (SKETCH_TOL[prec] * bound + (U32 * np.abs(Yo) if prec != P.FP64 else 0))
+    assert np.max(err) <= 0, f"max excess {np.max(err):.3e}, max rel {np.max(np.abs(Y - Yo) / bound):.3e}"
+
+
 def test_sketch_rows_and_columns_are_independent(M):
     # permuting nothing but checking that each output column only sees its own input column
     m, n, s = 3000, 40, 80
@@ -67,8 +86,6 @@ def test_sketch_rows_and_columns_are_independent(M):
                                        (300, 40, 1e2), (512, 64, 1e3), (250, 128, 1e4), (1024, 32, 1e3),
                                        (2048, 16, 1e5), (1, 1, 1.0)])
 def test_sketch_qr_matches_householder(M, qrp, s, n, kappa):
-    if qrp == "fp32" and kappa > 1e6:
-        pytest.skip("float32 QR of a kappa=1e8 matrix is outside its accuracy range")
     progress(f"sketch_qr {qrp} s={s} n={n} kappa={kappa:g}")
     Yh = W.test_matrix(s, n, kappa, 4 + n)
     if qrp == "fp32":
@@ -76,9 +93,17 @@ def test_sketch_qr_matches_householder(M, qrp, s, n, kappa):
     Rs, kap = M.sketch_qr(to_dev(Yh), qrp)
     torch.cuda.synchronize()
     R = to_host(Rs)
-    _, Ro = HH.householder_qr(Yh)
     u = U64 if qrp == "fp64" else U32
     assert np.all(np.tril(R, -1) == 0) and np.all(np.diag(R) > 0)
+    if qrp == "fp32":
+        # the QR runs in single precision (Section "Algorithm Description")
+        assert np.array_equal(R, R.astype(np.float32).astype(np.float64))
+    # backward stability, independent of kappa: R^T R = (Y + dY)^T (Y + dY)
+    ny = np.linalg.norm(Yh, 2)
+    assert np.linalg.norm(R.T @ R - Yh.T @ Yh, 2) <= 40 * n * u * ny * ny
+    if qrp == "fp32" and kappa > 1e6:
+        return  # the forward error n u32 kappa says nothing at kappa = 1e8
+    _, Ro = HH.householder_qr(Yh)
     assert np.linalg.norm(R - Ro) / np.linalg.norm(Ro) <= 20 * n * u * kappa
     ko = CE.kappa_est(Ro)
     assert abs(float(to_host(kap)[0]) - ko) <= max(1e-6, 40 * n * u * kappa) * ko

@@ -274,3 +274,15 @@ def test_accepted_results_meet_the_target_and_estimate_is_tight():
                         accepted += 1
                         assert MT.orthogonality(r.Q) <= CLAIMS["target_orthogonality"]
     assert accepted > 50
+
+
+@pytest.mark.parametrize("prec,kappa", [(P.FP64, 1e8), (P.FP32, 1e6), (P.FP16, 1e3)])
+def test_rfft_sketch_gives_the_unique_qr(mats, prec, kappa):
+    """With the paper's operator (real DFT bins, c = 3n) the factorization is
+    the same unique thin QR."""
+    A = mats[kappa] if kappa in mats else W.test_matrix(m, n, kappa, 21)
+    r = M.factor(A, prec, seed=31, transform=M.RFFT)
+    assert r.status == M.STATUS_OK
+    Qh, Rh = M.reference_qr(A)
+    assert MT.rel_diff(r.R, Rh) < 50 * n * 2.0 ** -53 * kappa
+    assert MT.orthogonality(r.Q) < CLAIMS["target_orthogonality"]

@@ -112,3 +112,39 @@ def test_sketch_of_unit_vectors_matches_hand_derived_values(fmt, prec):
     Y = SK.sketch(A, np.array([1, 2]), d, prec)
     for (i, j), y in want.items():
         assert Y[i, j] == y, (fmt, i, j, Y[i, j].hex(), y.hex())
+
+
+def test_rfft_sketch_matches_numpy_rfft():
+    """The paper's operator: sqrt(c/m) Re(rfft(D A))[S] (numpy's DFT,
+    exp(-2 pi i k t / m) summed over t), bins from {0..m/2}, odd and even m."""
+    for m in [1000, 1001]:
+        n, c = 7, 21
+        A = W.gaussian(m, n, 11)
+        S = rng.sample_rows(3, m // 2 + 1, c)
+        d = rng.signs(3, m)
+        Y = SK.sketch_rfft(A, S, d, P.FP64)
+        ref = np.sqrt(c / m) * np.real(np.fft.rfft(d[:, None] * A, axis=0))[S, :]
+        assert np.max(np.abs(Y - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_rfft_phase_is_exact_for_large_m():
+    m = (1 << 21) + 5
+    k = np.array([m // 2, 12345, 1])
+    t = np.array([m - 1, 0, 777])
+    ph = SK.rfft_phase(k, t, m)
+    for i, kk in enumerate(k):
+        for j, tt in enumerate(t):
+            assert ph[i, j] == (4 * int(tt) * int(kk)) % (4 * m)
+
+
+@pytest.mark.parametrize("prec", [P.FP32, P.FP16, P.BF16])
+def test_low_precision_rfft_sketch_rounds_coefficients(prec):
+    # k = 0 gives cos = 1 at every t (exact in every format): Y is
+    # sqrt(c/m) times the column sums of fl_p(D A), rounded to float32
+    m, n = 512, 3
+    A = W.gaussian(m, n, 12)
+    d = rng.signs(4, m)
+    S = np.array([0, 5, 9])
+    Y = SK.sketch_rfft(A, S, d, prec)
+    at = SK.signed_cast(A, d, prec)
+    assert np.array_equal(Y[0], P.to_f32(np.sqrt(3 / m) * at.sum(axis=0)))
