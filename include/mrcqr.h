@@ -360,6 +360,32 @@ int mrcqr_condest(const double* R, int64_t n, int64_t ldr, double* kappa_dev, vo
 int mrcqr_posterior_kappa(const double* R, const double* X, int64_t n, int64_t ld, double* kappa_dev,
                           void* stream);
 
+/* The two other condition estimators of Section "Adaptive Precision
+ * Selection" (for comparison with the ICE estimate the policy uses).
+ *
+ * Block 1-norm estimator (Higham and Tisseur 2000, Algorithm 2.4; t = 2
+ * columns, at most 5 iterations, random +-1 columns from the counter-based
+ * generator of `seed`, stream 3). With G == NULL: kappa_dev receives
+ * ||R||_1 times the estimate of ||R^{-1}||_1 for an upper-triangular n x n
+ * R (e.g. Rs). With G != NULL (n x n symmetric A^T A, R its Cholesky factor):
+ * kappa_dev receives sqrt(n ||G||_1 est ||G^{-1}||_1), the paper's bound
+ * kappa_2(A)^2 <= n ||A^T A||_1 ||(A^T A)^{-1}||_1. Both matrices share the
+ * leading dimension ld; n <= 128. One wave; the estimate of the inverse's
+ * norm is a lower bound (usually within a factor 3). */
+int mrcqr_condest_1norm(const double* R, const double* G, int64_t n, int64_t ld, uint64_t seed,
+                        double* kappa_dev, void* stream);
+
+/* CholQR probe: one pass of Algorithm 1 on A (m x n, lda), then
+ * kappa_dev = sqrt(q / (u (1 + q))) with u = 2^-53 and q = ||I - Q^T Q||_2
+ * estimated by 12 power steps (a lower estimate, so the bound stays a lower
+ * bound on kappa_2(A)); +inf when the pass breaks down (the Gram matrix is
+ * not numerically positive definite: kappa_2(A) beyond about 1e8). Needs
+ * mrcqr_cholqr_probe_workspace_bytes(m, n) bytes of device workspace (Q and
+ * small terms, about m n 8 bytes). */
+size_t mrcqr_cholqr_probe_workspace_bytes(int64_t m, int64_t n);
+int mrcqr_cholqr_probe(const double* A, int64_t m, int64_t n, int64_t lda, void* workspace,
+                       size_t workspace_bytes, double* kappa_dev, void* stream);
+
 const char* mrcqr_status_string(int status);
 /* Library version as major * 10000 + minor * 100 + patch. */
 int mrcqr_version(void);

@@ -157,6 +157,7 @@ def onenorm_est(apply, apply_t, n: int, t: int = 2, itmax: int = 5, seed: int = 
     if n == 1:
         return float(abs(apply(np.ones((1, 1)))[0, 0]))
     t = min(t, n)
+    tries = 16  # random draws for one column before the last one is kept (small n may have no other choice)
     rcol = [0]
 
     def fresh():
@@ -169,9 +170,10 @@ def onenorm_est(apply, apply_t, n: int, t: int = 2, itmax: int = 5, seed: int = 
 
     X = np.ones((n, t))
     for j in range(1, t):
-        c = fresh()
-        while any(parallel(c, X[:, i]) for i in range(j)):
+        for _ in range(tries):
             c = fresh()
+            if not any(parallel(c, X[:, i]) for i in range(j)):
+                break
         X[:, j] = c
     X /= n
     est_old = 0.0
@@ -197,8 +199,10 @@ def onenorm_est(apply, apply_t, n: int, t: int = 2, itmax: int = 5, seed: int = 
         if k > 1 and all(any(parallel(S[:, j], S_old[:, i]) for i in range(t)) for j in range(t)):
             break
         for j in range(t):
-            while any(parallel(S[:, j], S[:, i]) for i in range(j)) or \
-                    (k > 1 and any(parallel(S[:, j], S_old[:, i]) for i in range(t))):
+            for _ in range(tries):
+                if not (any(parallel(S[:, j], S[:, i]) for i in range(j)) or
+                        (k > 1 and any(parallel(S[:, j], S_old[:, i]) for i in range(t)))):
+                    break
                 S[:, j] = fresh()
         S_old = S.copy()
         Z = apply_t(S)
@@ -251,13 +255,28 @@ def cholqr_probe(q: float, u: float = 2.0 ** -53) -> float:
     return float(np.sqrt(q / (u * (1.0 + q))))
 
 
-def probe_kappa(A: np.ndarray) -> float:
-    """The CholQR probe on A: one pass of Algorithm 1, q from its Q, the
-    bound above; +inf when the pass breaks down (kappa(A) beyond about
-    u^(-1/2), the double regime)."""
+def sym_power_norm(E: np.ndarray, steps: int = POWER_STEPS) -> float:
+    """||E x|| after `steps` normalized applications of the symmetric E to
+    x0 = ones/sqrt(n): a lower bound on ||E||_2."""
+    E = np.asarray(E, dtype=np.float64)
+    x = np.full(E.shape[0], 1.0 / np.sqrt(E.shape[0]))
+    for _ in range(steps):
+        z = E @ x
+        x = z / np.linalg.norm(z)
+    return float(np.linalg.norm(E @ x))
+
+
+def probe_kappa(A: np.ndarray, exact: bool = True) -> float:
+    """The CholQR probe on A: one pass of Algorithm 1, q = ||I - Q^T Q||_2
+    of its Q (exact, or by sym_power_norm as the GPU estimates it), the bound
+    above; +inf when the pass breaks down (kappa(A) beyond about u^(-1/2),
+    the double regime)."""
     from . import cholqr as CQ, metrics as MT
     try:
         Q, _ = CQ.cholqr(A)
     except CQ.CholeskyBreakdown:
         return float("inf")
-    return cholqr_probe(MT.orthogonality(Q))
+    if exact:
+        return cholqr_probe(MT.orthogonality(Q))
+    E = np.eye(Q.shape[1]) - CQ.gram(Q)
+    return cholqr_probe(sym_power_norm(E))

@@ -75,6 +75,9 @@ def lib() -> ctypes.CDLL:
             "mrcqr_condest": (i32, [vp, i64, i64, vp, vp]),
             "mrcqr_posterior_kappa": (i32, [vp, vp, i64, i64, vp, vp]),
             "mrcqr_release_cache": (i32, []),
+            "mrcqr_condest_1norm": (i32, [vp, vp, i64, i64, u64, vp, vp]),
+            "mrcqr_cholqr_probe_workspace_bytes": (sz, [i64, i64]),
+            "mrcqr_cholqr_probe": (i32, [vp, i64, i64, i64, vp, sz, vp, vp]),
             "mrcqr_regime_reset": (i32, [vp, vp, sz, vp]),
             "mrcqr_batch_plan_create": (i32, [i32, vp, vp, ctypes.POINTER(vp)]),
             "mrcqr_batch_plan_workspace_bytes": (sz, [vp]),
@@ -508,6 +511,35 @@ def posterior_kappa(R: torch.Tensor, X: torch.Tensor, stream=None) -> torch.Tens
     kappa = torch.empty(1, dtype=torch.float64, device=R.device)
     _check(lib().mrcqr_posterior_kappa(R.data_ptr(), X.data_ptr(), n, _ld(R), kappa.data_ptr(), _stream(stream)),
            "mrcqr_posterior_kappa")
+    return kappa
+
+
+def condest_1norm(R: torch.Tensor, G: torch.Tensor | None = None, seed: int = 0, stream=None) -> torch.Tensor:
+    """Block 1-norm estimate: kappa_1(R), or (with G = R^T R) the paper's bound
+    sqrt(n ||G||_1 ||G^{-1}||_1)."""
+    n = R.shape[0]
+    _mat(R, n, n, "R")
+    if G is not None:
+        _mat(G, n, n, "G")
+        if _ld(G) != _ld(R):
+            raise ValueError("R and G must have the same leading dimension")
+    _same_cuda_device([("R", R)] + ([("G", G)] if G is not None else []))
+    kappa = torch.empty(1, dtype=torch.float64, device=R.device)
+    _check(lib().mrcqr_condest_1norm(R.data_ptr(), G.data_ptr() if G is not None else None, n, _ld(R),
+                                     seed & (2 ** 64 - 1), kappa.data_ptr(), _stream(stream)), "mrcqr_condest_1norm")
+    return kappa
+
+
+def cholqr_probe(A: torch.Tensor, stream=None) -> torch.Tensor:
+    """The CholQR probe's lower bound on kappa_2(A) (+inf on breakdown)."""
+    m, n = A.shape
+    _mat(A, m, n, "A")
+    _same_cuda_device([("A", A)])
+    wsb = int(lib().mrcqr_cholqr_probe_workspace_bytes(m, n))
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=A.device)
+    kappa = torch.empty(1, dtype=torch.float64, device=A.device)
+    _check(lib().mrcqr_cholqr_probe(A.data_ptr(), m, n, _ld(A), ws.data_ptr(), wsb, kappa.data_ptr(),
+                                    _stream(stream)), "mrcqr_cholqr_probe")
     return kappa
 
 

@@ -45,6 +45,11 @@ hipError_t launch_posterior_grouped(const BatchInst* bi, const int32_t* members,
                                     int phase, hipStream_t st);
 hipError_t launch_ctrl_finalize(const Ctrl* ctrl, void* info, hipStream_t st);
 hipError_t launch_cholqr2_finalize(const int32_t* fail, void* info, hipStream_t st);
+hipError_t launch_onenorm_condest(const double* R, const double* G, int n, int64_t ld, uint64_t seed,
+                                  double* kappa, hipStream_t st);
+size_t probe_workspace_bytes(int64_t m, int64_t n);
+hipError_t launch_cholqr_probe(const double* A, int m, int n, int64_t lda, void* ws, double* kappa,
+                               hipStream_t st);
 // grouped launches over the members of a batch
 hipError_t launch_draw_grouped(const BatchInst* bi, const int32_t* members, int count, int max_s,
                                const BatchCall& call, hipStream_t st);
@@ -774,6 +779,26 @@ int mrcqr_cholqr2(const double* A, int64_t m, int64_t n, int64_t lda, double* Q,
       launch_trmm(R2, n, R1, n, ni, R, ldr, nullptr, PH_FIRST, st) == hipSuccess &&
       (!info_dev || launch_cholqr2_finalize(fail, info_dev, st) == hipSuccess);
   return ok ? MRCQR_OK : MRCQR_ERR_DEVICE;
+}
+
+int mrcqr_condest_1norm(const double* R, const double* G, int64_t n, int64_t ld, uint64_t seed, double* kappa_dev,
+                        void* stream) {
+  if (!R || !kappa_dev || n < 1 || ld < n) return MRCQR_ERR_ARG;
+  if (n > NMAX) return MRCQR_ERR_UNSUPPORTED;
+  return hip_status(launch_onenorm_condest(R, G, (int)n, ld, seed, kappa_dev, as_stream(stream)));
+}
+
+size_t mrcqr_cholqr_probe_workspace_bytes(int64_t m, int64_t n) {
+  if (n < 1 || m < n || n > NMAX || m >= MMAX) return 0;
+  return probe_workspace_bytes(m, n);
+}
+
+int mrcqr_cholqr_probe(const double* A, int64_t m, int64_t n, int64_t lda, void* workspace, size_t workspace_bytes,
+                       double* kappa_dev, void* stream) {
+  if (!A || !kappa_dev || n < 1 || m < n || lda < m) return MRCQR_ERR_ARG;
+  if (n > NMAX || m >= MMAX) return MRCQR_ERR_UNSUPPORTED;
+  if (!workspace || workspace_bytes < probe_workspace_bytes(m, n)) return MRCQR_ERR_WORKSPACE;
+  return hip_status(launch_cholqr_probe(A, (int)m, (int)n, lda, workspace, kappa_dev, as_stream(stream)));
 }
 
 const char* mrcqr_status_string(int status) {

@@ -292,3 +292,43 @@ def test_paper_sweep_matrix_has_the_stated_spectrum():
     A = W.paper_sweep_matrix(4096, 50, 1e10, 74)
     sv = np.linalg.svd(A, compute_uv=False)
     assert abs(sv[0] / 1e5 - 1) < 1e-12 and abs(sv[-1] / 1e-5 - 1) < 1e-5
+
+
+def test_block_onenorm_estimator_is_exact_on_diagonals_and_a_lower_bound():
+    d = np.array([0.5, -7.0, 2.0, 3.0, -1.0])
+    D = np.diag(d)
+    est = CE.onenorm_est(lambda X: D @ X, lambda X: D.T @ X, 5)
+    assert est == 7.0
+    import scipy.linalg
+    for kappa in [10.0, 1e4, 1e9]:
+        for sd in range(8):
+            R = W.upper_triangular(30, kappa, 200 + sd)
+            Ri = np.linalg.inv(R)
+            exact = np.abs(Ri).sum(axis=0).max()
+            est = CE.onenorm_est(lambda X: scipy.linalg.solve_triangular(R, X),
+                                 lambda X: scipy.linalg.solve_triangular(R, X, trans="T"), 30, seed=sd)
+            assert exact / 3 <= est <= exact * (1 + 1e-10)
+
+
+def test_estimators_bracket_the_condition_number():
+    """kappa_1(R) lies in [kappa_2(R)/n, n kappa_2(R)] (norm equivalence) and
+    the Gram bound sqrt(n kappa_1(A^T A)) is at least kappa_2(A) when the
+    inverse's norm is estimated exactly; the CholQR probe is a lower bound."""
+    import scipy.linalg
+    m_, n_ = 4096, 20
+    for kappa in [1e2, 1e5]:
+        A = W.test_matrix(m_, n_, kappa, 300)
+        R = CQ.cholesky_upper(A.T @ A)
+        k1 = CE.kappa_1norm_tri(R)
+        k2 = kappa
+        assert k2 / n_ <= k1 <= n_ * k2 * (1 + 1e-6)
+        kb = CE.kappa_bound_gram(R)
+        assert kb >= 0.5 * k2
+        kp = CE.probe_kappa(A)
+        assert kp <= k2 * (1 + 1e-6)
+    assert CE.probe_kappa(W.paper_sweep_matrix(m_, n_, 1e12, 301)) == float("inf")
+
+
+def test_probe_power_estimate_is_below_the_exact_one():
+    A = W.test_matrix(4096, 16, 1e5, 302)
+    assert CE.probe_kappa(A, exact=False) <= CE.probe_kappa(A, exact=True) * (1 + 1e-9)
