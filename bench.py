@@ -193,19 +193,23 @@ def main() -> int:
     Rs = torch.from_numpy(np.ascontiguousarray(np.triu(R.cpu().numpy()).T)).cuda().t()
     X = M.empty_colmajor(m, n)
     tws = torch.empty(int(M.lib().mrcqr_trsm_workspace_bytes(n)), dtype=torch.uint8, device="cuda")
-    for _ in range(3):
+    for _ in range(10):
         M.trsm(A, Rs, X, workspace=tws)
     torch.cuda.synchronize()
-    # back-to-back launches between two events on the library's stream; one
-    # launch = the R staging kernel (a few us) + trsm_kernel
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.steps):
-        M.trsm(A, Rs, X, workspace=tws)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    trsm_ms = e0.elapsed_time(e1) / args.steps
+    # back-to-back launches between two events on the library's stream, in
+    # five rounds of `steps` launches (median round); one launch = the R
+    # staging kernel (a few us) + trsm_kernel
+    rounds = []
+    for _ in range(5):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            M.trsm(A, Rs, X, workspace=tws)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        rounds.append(e0.elapsed_time(e1) / args.steps)
+    trsm_ms = sorted(rounds)[len(rounds) // 2]
     trsm_bytes = 2.0 * 8.0 * m * n  # read A, write X (algorithmic)
     achieved = trsm_bytes / (trsm_ms * 1e-3) / 1e9
     log(f"trsm kernel: {trsm_ms:.4f} ms/launch, {achieved:.1f} GB/s")
@@ -249,7 +253,7 @@ def main() -> int:
                            "fp64": round(flop_2mn2 / (ms64 * 1e-3) / 1e9, 2)},
         "fp64_mfma_roofline_frac_3mn2": round(3.0 * m * n * n / (ms16 * 1e-3) / (FP64_PEAK_TFLOPS * 1e12), 4),
         "accuracy": acc,
-        "roofline": {"kernel": "trsm_kernel<128> (X = A R^-1, float64)", "bound": "hbm",
+        "roofline": {"kernel": "trsm_kernel<8> (X = A R^-1, float64, 8 column blocks of 16)", "bound": "hbm",
                      "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": (round(trsm_traffic_bytes() / 1e9, 4) if (m, n) == (1 << 20, 128) and
