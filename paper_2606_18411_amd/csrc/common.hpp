@@ -35,21 +35,6 @@ __device__ __forceinline__ f64x4 mfma_f64(double a, double b, f64x4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// Raw buffer resource over `bytes` bytes at p (stride 0; dword 3 selects a
-// 32-bit data format, no swizzle). An access at a byte offset at or beyond
-// `bytes` reads zero and writes nothing, so a descriptor per column with the
-// valid byte count masks rows and columns without per-lane predicates.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, (int)bytes, 0x00020000);
-}
-typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ double buf_ld64(__amdgpu_buffer_rsrc_t rs, uint32_t voff) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rs, (int)voff, 0, 0));
-}
-__device__ __forceinline__ void buf_st64(double v, __amdgpu_buffer_rsrc_t rs, uint32_t voff) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), rs, (int)voff, 0, 0);
-}
-
 // f(integral_constant<0>), ..., f(integral_constant<N-1>), in this order
 template <int N, typename F>
 __device__ __forceinline__ void static_for(F&& f) {
