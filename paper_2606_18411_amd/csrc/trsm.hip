@@ -74,18 +74,17 @@ __device__ __forceinline__ void trsm_prep_body(const double* __restrict__ R, int
     Rb[r][c] = (o + r < n && o + c < n) ? R[(o + r) + (int64_t)(o + c) * ldr] : 0.0;
     __syncthreads();
     if (t < 16) {
-      // column i = t of inv(R_JJ), zero beyond n
+      // column i = t of inv(R_JJ), zero beyond n (fixed trip counts with
+      // predicates keep x in registers)
       const int i = t;
+      const bool live = o + i < n;
       double x[16];
 #pragma unroll
-      for (int k = 0; k < 16; ++k) x[k] = 0.0;
-      if (o + i < n) {
-        x[i] = 1.0 / Rb[i][i];
-        for (int k = i - 1; k >= 0; --k) {
-          double acc = 0.0;
-          for (int u = k + 1; u <= i; ++u) acc = fma(Rb[k][u], x[u], acc);
-          x[k] = -acc / Rb[k][k];
-        }
+      for (int k = 15; k >= 0; --k) {
+        double acc = 0.0;
+#pragma unroll
+        for (int u = k + 1; u < 16; ++u) acc = u <= i ? fma(Rb[k][u], x[u], acc) : acc;
+        x[k] = !live || k > i ? 0.0 : (k == i ? 1.0 : -acc) / Rb[k][k];
       }
 #pragma unroll
       for (int k = 0; k < 16; ++k) Dinv[256 * J + 64 * (k / 4) + 16 * (k % 4) + i] = x[k];
