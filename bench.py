@@ -32,15 +32,15 @@ METRIC = "ms/QR at m=2^20,n=128: FP16-sketch vs FP64-sketch at â€–Iâˆ’Qáµ€Qâ€–â‰
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
-# HBM traffic of one trsm_kernel<128> launch at m = 2^20, n = 128 from two
+# HBM traffic of one trsm_kernel<8> launch at m = 2^20, n = 128 from two
 # rocprofv3 counter runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) of
 # this script with --copy-calibration, each scaled by what the counter reads
 # for the 256 MiB device copy of that run (FETCH_SIZE reads half the copied
 # bytes, WRITE_SIZE all of them); profiles/trsm_kernel_traffic_m1048576_n128.md
 # holds the numbers. Reported only while the kernel source is the one the
 # counters were taken on.
-TRSM_TRAFFIC = {"fetch_kib": 525176.2, "fetch_factor": 2.0, "write_kib": 1048576.3, "write_factor": 1.0,
-                "source_sha256": "7b65543dc32ff2384c64978fc4ff9656f255a9793b056d556c326a40de5a974d"}
+TRSM_TRAFFIC = {"fetch_kib": 524688.8, "fetch_factor": 2.0, "write_kib": 1048576.1, "write_factor": 1.0,
+                "source_sha256": "72b6cdd30505b5fcc7b89f225effa9235157cb849f743d51c34dbf732c05b23e"}
 
 
 def trsm_traffic_bytes():
