@@ -11,9 +11,11 @@
  *           of Y giving the preconditioner Rs;
  *   Stage 2 (float64): B = A Rs^{-1}, then Cholesky-QR of B (Algorithm 1):
  *           G = B^T B, G = Rc^T Rc, Q = B Rc^{-1};
- *           B = A Rs^{-1} is a substitution (Rs may be as ill conditioned as
- *           A); Q is the product of B with the explicit inverse of Rc,
- *           whose condition number is that of B, a small constant;
+ *           B = A Rs^{-1} is a block substitution (Rs may be as ill
+ *           conditioned as A, so Rs itself is never inverted; only its
+ *           16 x 16 diagonal blocks are, as GPU triangular solves do); Q is
+ *           the product of B with the explicit inverse of Rc, whose
+ *           condition number is that of B, a small constant;
  *   Stage 3: R = Rc Rs.
  *
  * Conventions for every entry point:
@@ -157,7 +159,7 @@ int mrcqr_factor(const double* A, int64_t m, int64_t n, int64_t lda,
 /* CholQR2, the unpreconditioned baseline of the paper's stability sweep
  * (Section "Numerical Stability"): Algorithm 1 applied twice, [Q1, R1] =
  * CholQR(A), [Q, R2] = CholQR(Q1), R = R2 R1, every step in float64 on the
- * library's kernels (Gram SYRK, Cholesky, substitution Q = A R^{-1}). It
+ * library's kernels (Gram SYRK, Cholesky, block substitution Q = A R^{-1}). It
  * breaks down once the Gram matrix of A is not numerically positive definite
  * (kappa(A) past about 1e8): info->status = MRCQR_ERR_CHOL_BREAKDOWN with the
  * first failing pivot (of pass 1, else of pass 2), and Q, R unspecified.
@@ -305,9 +307,11 @@ int mrcqr_sketch_ex(const double* A, int64_t m, int64_t n, int64_t lda,
 int mrcqr_sketch_qr(const double* Y, int64_t s, int64_t n, int64_t ldy, int qr_precision,
                     double* Rs, int64_t ldr, double* kappa_dev, void* stream);
 
-/* Stage 2 triangular solve X = A R^{-1} (R upper, n x n), by blocked
- * substitution (no inverse of R is formed; Section "Algorithm
- * Description"). X must not overlap A. Needs
+/* Stage 2 triangular solve X = A R^{-1} (R upper, n x n), by block
+ * substitution over column blocks of 16: X_J = (A_J - X_{<J} R_{<J,J})
+ * inv(R_JJ). No inverse of R is formed (Section "Algorithm Description");
+ * only the 16 x 16 diagonal blocks are inverted (by substitution), as GPU
+ * triangular solves do. X must not overlap A. Needs
  * mrcqr_trsm_workspace_bytes(n) bytes of device workspace (R staged in
  * operand order; about 75 KB at n = 128). */
 size_t mrcqr_trsm_workspace_bytes(int64_t n);
