@@ -246,6 +246,7 @@ def main() -> int:
         "config": {"workload": f"MRCQR thin QR, m={m}, n={n}, s={s}, kappa={kappa:g}, A=U diag(sigma) V^T",
                    "m": m, "n": n, "s": s, "kappa": kappa, "sketch_precision": "fp16"},
         "fp64_sketch_ms_per_qr": round(ms64, 5),
+        "fp64_sketch_variant": "dense float64 MFMA contraction against generated DCT-II rows (no butterfly variant is built)",
         "auto_ms_per_qr": round(ms_auto, 5),
         "auto_precision_used": acc["auto"]["precision_used"],
         "fp16_over_fp64_speedup": round(ms64 / ms16, 4),
