@@ -78,14 +78,38 @@ hipError_t launch_finalize_grouped(const BatchInst* bi, const int32_t* members, 
                                    hipStream_t st);
 struct SketchGeom { int chunks, rows_per_chunk; };
 SketchGeom sketch_geometry(int64_t m);
+// the column-panel path for 128 < n <= 512 (csrc/wide.hip)
+hipError_t launch_sketch_qr_wide(bool f64, double* Y, int s, int n, int64_t ldy, double* Rs, int64_t ldr,
+                                 double* tau, int* flags, double* kappa, Ctrl* ctrl, int slot, int phase,
+                                 hipStream_t st);
+hipError_t launch_trsm_wide(const double* A, int m, int n, int64_t lda, const double* R, int64_t ldr, double* X,
+                            int64_t ldx, void* ws, const Ctrl* ctrl, int phase, hipStream_t st);
+size_t gram_pair_partial_bytes(int n);
+hipError_t launch_gram_wide(const double* B, int m, int n, int64_t ldb, double* Gpart_diag, double* Gpart_pairs,
+                            double* G, int64_t ldg, const Ctrl* ctrl, int phase, hipStream_t st);
+hipError_t launch_cholesky_wide(double* G, int n, int64_t ldg, double* Rc, int64_t ldr, int32_t* fail,
+                                double* kappa, double* T, int32_t* fails, void* Tw, Ctrl* ctrl, int phase,
+                                hipStream_t st);
+hipError_t launch_rc_tail_wide(const double* Rc, int n, int64_t ldc, const double* Rs, int64_t lds_, double* X,
+                               int64_t ldx, double* R, int64_t ldr, const Ctrl* ctrl, int phase, hipStream_t st);
+hipError_t launch_trinv_wide(const double* R, int n, int64_t ldr, double* X, int64_t ldx, const Ctrl* ctrl, int phase,
+                             hipStream_t st);
+hipError_t launch_trmm_wide(const double* R2, int64_t ld2, const double* R1, int64_t ld1, int n, double* R,
+                            int64_t ldr, const Ctrl* ctrl, int phase, hipStream_t st);
+hipError_t launch_posterior_wide(const double* Rc, const double* X, int n, int64_t ld, Ctrl* ctrl, int phase,
+                                 double* kappa_out, hipStream_t st);
+hipError_t launch_qform_wide(const double* B, int m, int n, int64_t ldb, const double* X, int64_t ldx, double* Q,
+                             int64_t ldq, const Ctrl* ctrl, int phase, hipStream_t st);
 }  // namespace mrcqr
 
 using namespace mrcqr;
 
 namespace {
 
-constexpr int64_t NMAX = 128;
+constexpr int64_t NMAX = 512;   // whole factorization; 128 < n <= 512 takes the column-panel path
+constexpr int64_t NSTEP = 128;  // single-kernel steps (Cholesky, CholQR2, the estimators, batches)
 constexpr int64_t SMAX = 2048;
+constexpr int64_t SWIDE = 1024; // sketch rows of the column-panel sketch QR
 constexpr int64_t MMAX = (int64_t)1 << 28;
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -99,7 +123,7 @@ bool valid_prec(int p, bool allow_auto) {
 int check_shape(int64_t m, int64_t n, int64_t s) {
   if (n < 1 || m < n || s < n || s > m) return MRCQR_ERR_ARG;
   if (n > NMAX || s > SMAX || m >= MMAX) return MRCQR_ERR_UNSUPPORTED;
-  if (!qr_supported((int)s, (int)n)) return MRCQR_ERR_UNSUPPORTED;
+  if (n > NSTEP ? s > SWIDE : !qr_supported((int)s, (int)n)) return MRCQR_ERR_UNSUPPORTED;
   return MRCQR_OK;
 }
 
@@ -113,6 +137,10 @@ struct mrcqr_plan {
   int64_t m, n, s;
   int xform = 0;  // 0: DCT-II sketch; 1: real part of the DFT (MRCQR_SKETCH_RFFT)
   size_t off_ctrl, off_S, off_Ypart, off_Y, off_Rs, off_Gpart, off_G, off_Rc, off_Rci, off_Tw, off_B, total;
+  // column-panel path (n > 128): Householder tau and flags, the Gram's
+  // partials of the blocks above the diagonal, the Cholesky's panel and
+  // per-panel pivots
+  size_t off_tau = 0, off_flags = 0, off_Gpair = 0, off_T = 0, off_fails = 0;
 };
 
 static void plan_layout(mrcqr_plan* p) {
@@ -124,11 +152,19 @@ static void plan_layout(mrcqr_plan* p) {
   p->off_Ypart = take(sketch_partial_bytes(p->m, p->n, p->s, P_FP64));
   p->off_Y = take(s * n * sizeof(double));
   p->off_Rs = take(n * n * sizeof(double));
-  p->off_Gpart = take(gram_partial_bytes(p->m, p->n));
+  const bool wide = p->n > NSTEP;
+  p->off_Gpart = take(gram_partial_bytes(p->m, wide ? NSTEP : p->n));
   p->off_G = take(n * n * sizeof(double));
   p->off_Rc = take(n * n * sizeof(double));
   p->off_Rci = take(n * n * sizeof(double));
-  p->off_Tw = take(trsm_workspace_bytes((int)n));
+  p->off_Tw = take(trsm_workspace_bytes((int)std::min<int64_t>(p->n, NSTEP)));
+  if (wide) {
+    p->off_tau = take(n * sizeof(double));
+    p->off_flags = take(sizeof(int));
+    p->off_Gpair = take(gram_pair_partial_bytes((int)n));
+    p->off_T = take(n * NSTEP * sizeof(double));
+    p->off_fails = take(8 * sizeof(int32_t));
+  }
   p->off_B = take(m * n * sizeof(double));
   p->total = o;
 }
@@ -159,12 +195,26 @@ static int execute(const mrcqr_plan* p, char* ws, const double* A, int64_t lda, 
   // the kernels of an attempt whose precision is not the current one (or of
   // a rerun that was not requested) return immediately.
   auto stage1 = [&](int pp, int phase) -> bool {
-    return launch_sketch(pp, A, lda, m, n, S, s, seed, Ypart, Y, s, ctrl, phase, st, p->xform) == hipSuccess &&
-           launch_sketch_qr(pp == P_FP64, Y, s, n, s, Rs, n, nullptr, ctrl, pp, phase, st) == hipSuccess;
+    if (launch_sketch(pp, A, lda, m, n, S, s, seed, Ypart, Y, s, ctrl, phase, st, p->xform) != hipSuccess)
+      return false;
+    if (n > NSTEP)
+      return launch_sketch_qr_wide(pp == P_FP64, Y, s, n, s, Rs, n, reinterpret_cast<double*>(ws + p->off_tau),
+                                   reinterpret_cast<int*>(ws + p->off_flags), nullptr, ctrl, pp, phase, st) ==
+             hipSuccess;
+    return launch_sketch_qr(pp == P_FP64, Y, s, n, s, Rs, n, nullptr, ctrl, pp, phase, st) == hipSuccess;
   };
   // Stage 2 and 3 of one pass; Q is formed in the pass's tail phase, which
   // is skipped when the posterior check asks for a rerun
   auto stage2 = [&](int phase, int tail_phase) -> bool {
+    if (n > NSTEP)
+      return launch_trsm_wide(A, m, n, lda, Rs, n, B, ldb, Tw, ctrl, phase, st) == hipSuccess &&
+             launch_gram_wide(B, m, n, ldb, Gpart, reinterpret_cast<double*>(ws + p->off_Gpair), G, n, ctrl, phase,
+                              st) == hipSuccess &&
+             launch_cholesky_wide(G, n, n, Rc, n, nullptr, nullptr, reinterpret_cast<double*>(ws + p->off_T),
+                                  reinterpret_cast<int32_t*>(ws + p->off_fails), Tw, ctrl, phase, st) == hipSuccess &&
+             launch_rc_tail_wide(Rc, n, n, Rs, n, Rci, n, R, ldr, ctrl, phase, st) == hipSuccess &&
+             launch_posterior_wide(Rc, Rci, n, n, ctrl, phase, nullptr, st) == hipSuccess &&
+             launch_qform_wide(B, m, n, ldb, Rci, n, Q, ldq, ctrl, tail_phase, st) == hipSuccess;
     return launch_trsm(A, m, n, lda, Rs, n, B, ldb, Tw, ctrl, phase, st) == hipSuccess &&
            launch_gram(B, m, n, ldb, Gpart, G, n, ctrl, phase, st) == hipSuccess &&
            launch_cholesky(G, n, n, Rc, n, nullptr, nullptr, ctrl, phase, st) == hipSuccess &&
@@ -235,7 +285,8 @@ static int batch_plan_build(int32_t batch, const int64_t* m, const int64_t* n, m
   size_t o = 0;
   for (int32_t i = 0; i < batch; ++i) {
     const int64_t s = 2 * n[i];
-    const int c = check_shape(m[i], n[i], s);
+    int c = check_shape(m[i], n[i], s);
+    if (!c && n[i] > NSTEP) c = MRCQR_ERR_UNSUPPORTED;  // batches run the single-kernel steps
     if (c) { batch_plan_free(p); return c; }
     mrcqr_plan pl;
     pl.m = m[i]; pl.n = n[i]; pl.s = s;
@@ -654,27 +705,31 @@ int mrcqr_sketch_qr(const double* Y, int64_t s, int64_t n, int64_t ldy, int qr_p
                     int64_t ldr, double* kappa_dev, void* stream) {
   if (!Y || !Rs || n < 1 || s < n || ldy < s || ldr < n) return MRCQR_ERR_ARG;
   if (qr_precision != MRCQR_PREC_FP32 && qr_precision != MRCQR_PREC_FP64) return MRCQR_ERR_ARG;
-  if (n > NMAX || !qr_supported((int)s, (int)n)) return MRCQR_ERR_UNSUPPORTED;
+  if (n > NSTEP || !qr_supported((int)s, (int)n)) return MRCQR_ERR_UNSUPPORTED;
   return hip_status(launch_sketch_qr(qr_precision == MRCQR_PREC_FP64, Y, (int)s, (int)n, ldy, Rs, ldr, kappa_dev,
                                      nullptr, P_AUTO, PH_FIRST, as_stream(stream)));
 }
 
 size_t mrcqr_trsm_workspace_bytes(int64_t n) {
   if (n < 1 || n > NMAX) return 0;
-  return trsm_workspace_bytes((int)n);
+  return trsm_workspace_bytes((int)std::min<int64_t>(n, NSTEP));
 }
 
 int mrcqr_trsm(const double* A, int64_t m, int64_t n, int64_t lda, const double* R, int64_t ldr, double* X,
                int64_t ldx, void* workspace, size_t workspace_bytes, void* stream) {
   if (!A || !R || !X || m < 1 || n < 1 || lda < m || ldr < n || ldx < m || A == X) return MRCQR_ERR_ARG;
   if (n > NMAX || m >= MMAX) return MRCQR_ERR_UNSUPPORTED;
-  if (!workspace || workspace_bytes < trsm_workspace_bytes((int)n)) return MRCQR_ERR_WORKSPACE;
+  if (!workspace || workspace_bytes < mrcqr_trsm_workspace_bytes(n)) return MRCQR_ERR_WORKSPACE;
+  if (n > NSTEP)
+    return hip_status(launch_trsm_wide(A, (int)m, (int)n, lda, R, ldr, X, ldx, workspace, nullptr, PH_FIRST,
+                                       as_stream(stream)));
   return hip_status(launch_trsm(A, (int)m, (int)n, lda, R, ldr, X, ldx, workspace, nullptr, PH_FIRST,
                                 as_stream(stream)));
 }
 
 size_t mrcqr_gram_workspace_bytes(int64_t m, int64_t n) {
-  if (m < 1 || n < 1) return 0;
+  if (m < 1 || n < 1 || n > NMAX) return 0;
+  if (n > NSTEP) return align_up(gram_partial_bytes(m, NSTEP)) + gram_pair_partial_bytes((int)n);
   return gram_partial_bytes(m, n);
 }
 
@@ -682,7 +737,13 @@ int mrcqr_gram(const double* B, int64_t m, int64_t n, int64_t ldb, double* G, in
                size_t workspace_bytes, void* stream) {
   if (!B || !G || m < 1 || n < 1 || ldb < m || ldg < n) return MRCQR_ERR_ARG;
   if (n > NMAX || m >= MMAX) return MRCQR_ERR_UNSUPPORTED;
-  if (!workspace || workspace_bytes < gram_partial_bytes(m, n)) return MRCQR_ERR_WORKSPACE;
+  if (!workspace || workspace_bytes < mrcqr_gram_workspace_bytes(m, n)) return MRCQR_ERR_WORKSPACE;
+  if (n > NSTEP) {
+    double* diag = static_cast<double*>(workspace);
+    double* pairs = reinterpret_cast<double*>(static_cast<char*>(workspace) + align_up(gram_partial_bytes(m, NSTEP)));
+    return hip_status(launch_gram_wide(B, (int)m, (int)n, ldb, diag, pairs, G, ldg, nullptr, PH_FIRST,
+                                       as_stream(stream)));
+  }
   return hip_status(launch_gram(B, (int)m, (int)n, ldb, static_cast<double*>(workspace), G, ldg, nullptr,
                                 PH_FIRST, as_stream(stream)));
 }
@@ -690,7 +751,7 @@ int mrcqr_gram(const double* B, int64_t m, int64_t n, int64_t ldb, double* G, in
 int mrcqr_cholesky(const double* G, int64_t n, int64_t ldg, double* Rc, int64_t ldr, int32_t* fail_dev,
                    double* kappa_dev, void* stream) {
   if (!G || !Rc || n < 1 || ldg < n || ldr < n) return MRCQR_ERR_ARG;
-  if (n > NMAX) return MRCQR_ERR_UNSUPPORTED;
+  if (n > NSTEP) return MRCQR_ERR_UNSUPPORTED;
   return hip_status(launch_cholesky(G, (int)n, ldg, Rc, ldr, fail_dev, kappa_dev, nullptr, PH_FIRST,
                                     as_stream(stream)));
 }
@@ -699,12 +760,16 @@ int mrcqr_trmm(const double* R2, int64_t ld2, const double* R1, int64_t ld1, int
                void* stream) {
   if (!R2 || !R1 || !R || n < 1 || ld2 < n || ld1 < n || ldr < n) return MRCQR_ERR_ARG;
   if (n > NMAX) return MRCQR_ERR_UNSUPPORTED;
+  if (n > NSTEP)
+    return hip_status(launch_trmm_wide(R2, ld2, R1, ld1, (int)n, R, ldr, nullptr, PH_FIRST, as_stream(stream)));
   return hip_status(launch_trmm(R2, ld2, R1, ld1, (int)n, R, ldr, nullptr, PH_FIRST, as_stream(stream)));
 }
 
 int mrcqr_tri_inverse(const double* R, int64_t n, int64_t ldr, double* X, int64_t ldx, void* stream) {
   if (!R || !X || n < 1 || ldr < n || ldx < n || R == X) return MRCQR_ERR_ARG;
   if (n > NMAX) return MRCQR_ERR_UNSUPPORTED;
+  if (n > NSTEP)
+    return hip_status(launch_trinv_wide(R, (int)n, ldr, X, ldx, nullptr, PH_FIRST, as_stream(stream)));
   return hip_status(launch_trinv(R, (int)n, ldr, X, ldx, nullptr, PH_FIRST, as_stream(stream)));
 }
 
@@ -712,12 +777,14 @@ int mrcqr_form_q(const double* B, int64_t m, int64_t n, int64_t ldb, const doubl
                  int64_t ldq, void* stream) {
   if (!B || !X || !Q || m < 1 || n < 1 || ldb < m || ldx < n || ldq < m || B == Q) return MRCQR_ERR_ARG;
   if (n > NMAX || m >= MMAX) return MRCQR_ERR_UNSUPPORTED;
+  if (n > NSTEP)
+    return hip_status(launch_qform_wide(B, (int)m, (int)n, ldb, X, ldx, Q, ldq, nullptr, PH_FIRST, as_stream(stream)));
   return hip_status(launch_qform(B, (int)m, (int)n, ldb, X, ldx, Q, ldq, nullptr, PH_FIRST, as_stream(stream)));
 }
 
 int mrcqr_condest(const double* R, int64_t n, int64_t ldr, double* kappa_dev, void* stream) {
   if (!R || !kappa_dev || n < 1 || ldr < n) return MRCQR_ERR_ARG;
-  if (n > NMAX) return MRCQR_ERR_UNSUPPORTED;
+  if (n > NSTEP) return MRCQR_ERR_UNSUPPORTED;
   return hip_status(launch_condest(R, (int)n, ldr, kappa_dev, as_stream(stream)));
 }
 
@@ -725,6 +792,8 @@ int mrcqr_posterior_kappa(const double* R, const double* X, int64_t n, int64_t l
                           void* stream) {
   if (!R || !X || !kappa_dev || n < 1 || ld < n) return MRCQR_ERR_ARG;
   if (n > NMAX) return MRCQR_ERR_UNSUPPORTED;
+  if (n > NSTEP)
+    return hip_status(launch_posterior_wide(R, X, (int)n, ld, nullptr, PH_FIRST, kappa_dev, as_stream(stream)));
   return hip_status(launch_posterior(R, X, (int)n, ld, nullptr, PH_FIRST, kappa_dev, as_stream(stream)));
 }
 
@@ -749,14 +818,14 @@ static Cholqr2Layout cholqr2_layout(int64_t m, int64_t n) {
 }
 
 size_t mrcqr_cholqr2_workspace_bytes(int64_t m, int64_t n) {
-  if (n < 1 || m < n || n > NMAX || m >= MMAX) return 0;
+  if (n < 1 || m < n || n > NSTEP || m >= MMAX) return 0;
   return cholqr2_layout(m, n).total;
 }
 
 int mrcqr_cholqr2(const double* A, int64_t m, int64_t n, int64_t lda, double* Q, int64_t ldq, double* R,
                   int64_t ldr, void* workspace, size_t workspace_bytes, void* stream, mrcqr_info* info_dev) {
   if (!A || !Q || !R || n < 1 || m < n || lda < m || ldq < m || ldr < n || A == Q) return MRCQR_ERR_ARG;
-  if (n > NMAX || m >= MMAX) return MRCQR_ERR_UNSUPPORTED;
+  if (n > NSTEP || m >= MMAX) return MRCQR_ERR_UNSUPPORTED;
   const Cholqr2Layout L = cholqr2_layout(m, n);
   if (!workspace || workspace_bytes < L.total) return MRCQR_ERR_WORKSPACE;
   char* ws = static_cast<char*>(workspace);
@@ -784,19 +853,19 @@ int mrcqr_cholqr2(const double* A, int64_t m, int64_t n, int64_t lda, double* Q,
 int mrcqr_condest_1norm(const double* R, const double* G, int64_t n, int64_t ld, uint64_t seed, double* kappa_dev,
                         void* stream) {
   if (!R || !kappa_dev || n < 1 || ld < n) return MRCQR_ERR_ARG;
-  if (n > NMAX) return MRCQR_ERR_UNSUPPORTED;
+  if (n > NSTEP) return MRCQR_ERR_UNSUPPORTED;
   return hip_status(launch_onenorm_condest(R, G, (int)n, ld, seed, kappa_dev, as_stream(stream)));
 }
 
 size_t mrcqr_cholqr_probe_workspace_bytes(int64_t m, int64_t n) {
-  if (n < 1 || m < n || n > NMAX || m >= MMAX) return 0;
+  if (n < 1 || m < n || n > NSTEP || m >= MMAX) return 0;
   return probe_workspace_bytes(m, n);
 }
 
 int mrcqr_cholqr_probe(const double* A, int64_t m, int64_t n, int64_t lda, void* workspace, size_t workspace_bytes,
                        double* kappa_dev, void* stream) {
   if (!A || !kappa_dev || n < 1 || m < n || lda < m) return MRCQR_ERR_ARG;
-  if (n > NMAX || m >= MMAX) return MRCQR_ERR_UNSUPPORTED;
+  if (n > NSTEP || m >= MMAX) return MRCQR_ERR_UNSUPPORTED;
   if (!workspace || workspace_bytes < probe_workspace_bytes(m, n)) return MRCQR_ERR_WORKSPACE;
   return hip_status(launch_cholqr_probe(A, (int)m, (int)n, lda, workspace, kappa_dev, as_stream(stream)));
 }

@@ -173,4 +173,23 @@ __device__ double ice_kappa_block(const double* R, int n, int si, int sj, bool r
   return eM / em;
 }
 
+// ice_kappa_block for n <= 512 (4 or 8 columns per lane; the kernels of
+// the column-panel path for n > 128 call it, so that the register budget of
+// the n <= 128 kernels stays as it is).
+__device__ double ice_kappa_block_wide(const double* R, int n, int si, int sj, bool run) {
+  __shared__ double ice_res_w[2];
+  const int w = threadIdx.x >> 6;
+  if (run && w < 2) {
+    double est;
+    if (n <= 256) est = (w == 0) ? ice_est_wave<4, true>(R, n, si, sj) : ice_est_wave<4, false>(R, n, si, sj);
+    else est = (w == 0) ? ice_est_wave<8, true>(R, n, si, sj) : ice_est_wave<8, false>(R, n, si, sj);
+    if ((threadIdx.x & 63) == 0) ice_res_w[w] = est;
+  }
+  __syncthreads();
+  if (!run) return __builtin_nan("");
+  const double eM = ice_res_w[0], em = ice_res_w[1];
+  if (!isfinite(eM) || !isfinite(em) || !(em > 0.0)) return __builtin_inf();
+  return eM / em;
+}
+
 }  // namespace mrcqr

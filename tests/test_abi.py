@@ -53,7 +53,7 @@ def test_argument_errors_are_synchronous(lib):
              ((100, 10, 100, 7, 0, 100, 10), 1),    # bad precision
              ((100, 0, 100, 3, 0, 100, 1), 1),      # n = 0
              ((100, 10, 100, 3, 0, 100, 9), 1),     # ldr < n
-             ((1000, 200, 1000, 3, 0, 1000, 200), 8)]  # n above this library's limit
+             ((2000, 600, 2000, 3, 0, 2000, 600), 8)]  # n above this library's limit (512)
     for (m, n, lda, prec, s, ldq, ldr), want in cases:
         if want is None:
             continue
@@ -68,10 +68,10 @@ def test_step_entry_points_reject_shapes_synchronously(lib):
     vp, i64 = ctypes.c_void_p, ctypes.c_int64
     fake = ctypes.c_void_p(0x1000)
     lib.mrcqr_trmm.argtypes = [vp, i64, vp, i64, i64, vp, i64, vp]
-    assert lib.mrcqr_trmm(fake, 200, fake, 200, 200, fake, 200, None) == 8
+    assert lib.mrcqr_trmm(fake, 600, fake, 600, 600, fake, 600, None) == 8
     assert lib.mrcqr_trmm(fake, 10, fake, 10, 11, fake, 11, None) == 1
     lib.mrcqr_posterior_kappa.argtypes = [vp, vp, i64, i64, vp, vp]
-    assert lib.mrcqr_posterior_kappa(fake, fake, 200, 200, fake, None) == 8
+    assert lib.mrcqr_posterior_kappa(fake, fake, 600, 600, fake, None) == 8
     assert lib.mrcqr_posterior_kappa(fake, None, 20, 20, fake, None) == 1
     assert lib.mrcqr_posterior_kappa(fake, fake, 20, 19, fake, None) == 1
     # nothing cached in this process: releasing touches no device
