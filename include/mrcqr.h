@@ -358,11 +358,16 @@ int mrcqr_condest(const double* R, int64_t n, int64_t ldr, double* kappa_dev, vo
 /* Power-step part of the posterior estimate (Section "Adaptive Precision
  * Selection", rerun rule): kappa_dev receives sigma_max(R) sigma_max(X)
  * estimated by 12 power steps on R^T R and X^T X from the normalized
- * all-ones vector, for an upper-triangular n x n R (n <= 128) and X =
+ * all-ones vector, for an upper-triangular n x n R (n <= 512) and X =
  * R^{-1} (from mrcqr_tri_inverse), both with leading dimension ld. A lower
- * bound on kappa_2(R); +inf if a value is not finite. */
+ * bound on kappa_2(R); +inf if a value is not finite.
+ * workspace: device scratch of mrcqr_posterior_workspace_bytes(n) bytes
+ * (zero for n <= 128, where it may be NULL; for 128 < n <= 512 the power
+ * vectors, and MRCQR_ERR_WORKSPACE when it is NULL). Owned by the caller,
+ * not used after the stream reaches the end of the call. */
+size_t mrcqr_posterior_workspace_bytes(int64_t n);
 int mrcqr_posterior_kappa(const double* R, const double* X, int64_t n, int64_t ld, double* kappa_dev,
-                          void* stream);
+                          void* workspace, void* stream);
 
 /* The two other condition estimators of Section "Adaptive Precision
  * Selection" (for comparison with the ICE estimate the policy uses).

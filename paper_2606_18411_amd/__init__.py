@@ -73,7 +73,8 @@ def lib() -> ctypes.CDLL:
             "mrcqr_tri_inverse": (i32, [vp, i64, i64, vp, i64, vp]),
             "mrcqr_form_q": (i32, [vp, i64, i64, i64, vp, i64, vp, i64, vp]),
             "mrcqr_condest": (i32, [vp, i64, i64, vp, vp]),
-            "mrcqr_posterior_kappa": (i32, [vp, vp, i64, i64, vp, vp]),
+            "mrcqr_posterior_kappa": (i32, [vp, vp, i64, i64, vp, vp, vp]),
+            "mrcqr_posterior_workspace_bytes": (sz, [i64]),
             "mrcqr_release_cache": (i32, []),
             "mrcqr_condest_1norm": (i32, [vp, vp, i64, i64, u64, vp, vp]),
             "mrcqr_cholqr_probe_workspace_bytes": (sz, [i64, i64]),
@@ -509,7 +510,10 @@ def posterior_kappa(R: torch.Tensor, X: torch.Tensor, stream=None) -> torch.Tens
     if _ld(R) != _ld(X):
         raise ValueError("R and X must have the same leading dimension")
     kappa = torch.empty(1, dtype=torch.float64, device=R.device)
-    _check(lib().mrcqr_posterior_kappa(R.data_ptr(), X.data_ptr(), n, _ld(R), kappa.data_ptr(), _stream(stream)),
+    wsb = int(lib().mrcqr_posterior_workspace_bytes(n))
+    ws = torch.empty(wsb, dtype=torch.uint8, device=R.device) if wsb else None
+    _check(lib().mrcqr_posterior_kappa(R.data_ptr(), X.data_ptr(), n, _ld(R), kappa.data_ptr(),
+                                       ws.data_ptr() if ws is not None else None, _stream(stream)),
            "mrcqr_posterior_kappa")
     return kappa
 

@@ -96,8 +96,9 @@ hipError_t launch_trinv_wide(const double* R, int n, int64_t ldr, double* X, int
                              hipStream_t st);
 hipError_t launch_trmm_wide(const double* R2, int64_t ld2, const double* R1, int64_t ld1, int n, double* R,
                             int64_t ldr, const Ctrl* ctrl, int phase, hipStream_t st);
-hipError_t launch_posterior_wide(const double* Rc, const double* X, int n, int64_t ld, Ctrl* ctrl, int phase,
-                                 double* kappa_out, hipStream_t st);
+hipError_t launch_posterior_wide(const double* Rc, const double* X, int n, int64_t ld, double* ws, Ctrl* ctrl,
+                                 int phase, double* kappa_out, hipStream_t st);
+size_t posterior_wide_ws_bytes();
 hipError_t launch_qform_wide(const double* B, int m, int n, int64_t ldb, const double* X, int64_t ldx, double* Q,
                              int64_t ldq, const Ctrl* ctrl, int phase, hipStream_t st);
 }  // namespace mrcqr
@@ -213,7 +214,8 @@ static int execute(const mrcqr_plan* p, char* ws, const double* A, int64_t lda, 
              launch_cholesky_wide(G, n, n, Rc, n, nullptr, nullptr, reinterpret_cast<double*>(ws + p->off_T),
                                   reinterpret_cast<int32_t*>(ws + p->off_fails), Tw, ctrl, phase, st) == hipSuccess &&
              launch_rc_tail_wide(Rc, n, n, Rs, n, Rci, n, R, ldr, ctrl, phase, st) == hipSuccess &&
-             launch_posterior_wide(Rc, Rci, n, n, ctrl, phase, nullptr, st) == hipSuccess &&
+             launch_posterior_wide(Rc, Rci, n, n, reinterpret_cast<double*>(ws + p->off_T), ctrl, phase, nullptr,
+                                   st) == hipSuccess &&
              launch_qform_wide(B, m, n, ldb, Rci, n, Q, ldq, ctrl, tail_phase, st) == hipSuccess;
     return launch_trsm(A, m, n, lda, Rs, n, B, ldb, Tw, ctrl, phase, st) == hipSuccess &&
            launch_gram(B, m, n, ldb, Gpart, G, n, ctrl, phase, st) == hipSuccess &&
@@ -788,12 +790,19 @@ int mrcqr_condest(const double* R, int64_t n, int64_t ldr, double* kappa_dev, vo
   return hip_status(launch_condest(R, (int)n, ldr, kappa_dev, as_stream(stream)));
 }
 
+size_t mrcqr_posterior_workspace_bytes(int64_t n) {
+  return n > NSTEP && n <= NMAX ? posterior_wide_ws_bytes() : 0;
+}
+
 int mrcqr_posterior_kappa(const double* R, const double* X, int64_t n, int64_t ld, double* kappa_dev,
-                          void* stream) {
+                          void* workspace, void* stream) {
   if (!R || !X || !kappa_dev || n < 1 || ld < n) return MRCQR_ERR_ARG;
   if (n > NMAX) return MRCQR_ERR_UNSUPPORTED;
-  if (n > NSTEP)
-    return hip_status(launch_posterior_wide(R, X, (int)n, ld, nullptr, PH_FIRST, kappa_dev, as_stream(stream)));
+  if (n > NSTEP) {
+    if (!workspace) return MRCQR_ERR_WORKSPACE;
+    return hip_status(launch_posterior_wide(R, X, (int)n, ld, static_cast<double*>(workspace), nullptr, PH_FIRST,
+                                            kappa_dev, as_stream(stream)));
+  }
   return hip_status(launch_posterior(R, X, (int)n, ld, nullptr, PH_FIRST, kappa_dev, as_stream(stream)));
 }
 

@@ -31,89 +31,101 @@ constexpr int WD_PANEL = 128;  // column panel of the solve, Gram, Cholesky and 
 // ---------------------------------------------------------------------------
 // C = beta C0 + alpha Bs W: rows x nc (nc <= 128) from Bs (rows x K) and W
 // (K x nc; W(k, j) = W[k + j ldw], or W[j + k ldw] when TW). K is taken in
-// steps of 16; entries with k >= kvalid read as zero (Bs and W are never
+// chunks of 16; entries with k >= kvalid read as zero (Bs and W are never
 // read there). C0 may be C (each entry is read before it is written by the
 // same lane); beta == 0 reads no C0.
-// Each wave owns 16 rows (one tile) and all 8 column blocks of 16, 16 waves
-// (four per SIMD) share a workgroup; the transposed product C^T = W^T Bs^T
-// runs as float64 MFMA 16x16x4 with W (staged in LDS in A-operand order, 16
-// k at a time, double-buffered) as A operand and the rows of Bs as B
-// operand.
-constexpr int GP_THREADS = 1024;
-constexpr int GP_TILES = 1;
-constexpr int GP_ROWS = (GP_THREADS / 64) * 16 * GP_TILES;
+// Each wave owns 16 rows and all 8 column blocks of 16; 8 waves (two per
+// SIMD) share a workgroup and two workgroups a compute unit, so that one
+// workgroup's stores overlap the other's products. The transposed product
+// C^T = W^T Bs^T runs as float64 MFMA 16x16x4 with W (staged in LDS in
+// A-operand order, double-buffered, each chunk loaded into registers one
+// chunk ahead) as A operand and the rows of Bs (loaded one chunk ahead, and
+// the next pass's first chunk during the last one) as B operand.
+constexpr int GP_THREADS = 512;
+constexpr int GP_ROWS = (GP_THREADS / 64) * 16;
+constexpr int GP_WST = 2048 / GP_THREADS;  // W entries a thread stages per chunk
 
 template <bool TW>
-__global__ __launch_bounds__(GP_THREADS, 1) void gemm_panel_kernel(
+__global__ __launch_bounds__(GP_THREADS, 4) void gemm_panel_kernel(
     const double* __restrict__ Bs, int64_t ldb, int K, int kvalid, const double* __restrict__ W, int64_t ldw,
     const double* C0, int64_t ldc0, double* C, int64_t ldc, int rows, int nc, double alpha, double beta,
     const Ctrl* __restrict__ ctrl, int phase) {
-  __shared__ __attribute__((aligned(16))) double Wl[2][4 * 8 * 64];
+  __shared__ __attribute__((aligned(16))) double Wl[2][2048];
   if (skip_launch(ctrl, P_AUTO, phase)) return;
   const int tid = threadIdx.x;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63, g = l >> 4, c16 = l & 15;
   const int nch = (K + 15) / 16;
-  auto stage = [&](int buf, int k0) {
-    for (int e = tid; e < 4 * 8 * 64; e += GP_THREADS) {
-      const int ks = e / 512, b = (e / 64) % 8, ll = e % 64;
-      const int k = k0 + 4 * ks + ll / 16, j = 16 * b + ll % 16;
-      double v = 0.0;
-      if (j < nc && k < kvalid) v = TW ? W[j + (int64_t)k * ldw] : W[k + (int64_t)j * ldw];
-      Wl[buf][e] = v;
+  // W staging: entry e = tid + GP_THREADS q of a chunk sits at (k-step e / 512,
+  // column block (e / 64) % 8, lane e % 64) of the A-operand order
+  double wr[GP_WST];
+  // a lane's W base (row g, column c16 of a 4 x 16 piece) plus wave-uniform
+  // offsets: entry (k-step ks, column block b) of the chunk at k0
+  const double* Wlane = W + (TW ? c16 + (int64_t)g * ldw : g + (int64_t)c16 * ldw);
+  auto wload = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < GP_WST; ++q) {
+      const int e0 = 64 * w + GP_THREADS * q;  // first entry of this wave's q-th piece
+      const int ks = e0 >> 9, b = (e0 >> 6) & 7;
+      int64_t u = TW ? 16 * b + (int64_t)(k0 + 4 * ks) * ldw : (k0 + 4 * ks) + (int64_t)(16 * b) * ldw;
+      asm volatile("" : "+s"(u));
+      const bool in = 16 * b + c16 < nc && k0 + 4 * ks + g < kvalid;
+      wr[q] = in ? Wlane[u] : 0.0;
     }
   };
-  // a lane's addresses: its own base (row l%16, column l/16) plus
-  // wave-uniform offsets, stepped opaquely so that the optimizer does not
-  // keep per-lane 64-bit offsets of every k-step live
+  auto wstore = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < GP_WST; ++q) Wl[buf][tid + GP_THREADS * q] = wr[q];
+  };
   const double* Bl = Bs + c16 + (int64_t)g * ldb;
   const double* C0l = C0 + c16 + (int64_t)g * ldc0;
   double* Cl = C + c16 + (int64_t)g * ldc;
-  for (int64_t pan = blockIdx.x; pan * GP_ROWS < rows; pan += gridDim.x) {
-    const int64_t r0 = pan * GP_ROWS + 16 * GP_TILES * w;
+  double bd[4];
+  auto loadb = [&](int64_t r0, int k0) {
     const bool row_in = r0 + c16 < rows;
-    double bd[4][GP_TILES];
-    auto loadb = [&](int k0) {
-      int64_t u = r0 + (int64_t)k0 * ldb;
+    int64_t u = r0 + (int64_t)k0 * ldb;
 #pragma unroll
-      for (int ks = 0; ks < 4; ++ks) {
-        asm volatile("" : "+s"(u));
-        const bool in = row_in && k0 + 4 * ks + g < kvalid;
+    for (int ks = 0; ks < 4; ++ks) {
+      asm volatile("" : "+s"(u));
+      const bool in = row_in && k0 + 4 * ks + g < kvalid;
+      bd[ks] = in ? __builtin_nontemporal_load(&Bl[u]) : 0.0;
+      u += 4 * ldb;
+    }
+  };
+  int64_t pan = blockIdx.x;
+  if (pan * GP_ROWS >= rows) return;
+  wload(0);
+  loadb(pan * GP_ROWS + 16 * w, 0);
+  for (; pan * GP_ROWS < rows; pan += gridDim.x) {
+    const int64_t r0 = pan * GP_ROWS + 16 * w;
+    const int64_t rn = r0 + (int64_t)gridDim.x * GP_ROWS;  // this wave's rows in the next pass
+    const bool more = (pan + gridDim.x) * GP_ROWS < rows;
+    f64x4 acc[8];
 #pragma unroll
-        for (int t = 0; t < GP_TILES; ++t) bd[ks][t] = in ? Bl[u + 16 * t] : 0.0;
-        u += 4 * ldb;
-      }
-    };
-    f64x4 acc[8][GP_TILES];
-#pragma unroll
-    for (int b = 0; b < 8; ++b)
-#pragma unroll
-      for (int t = 0; t < GP_TILES; ++t) acc[b][t] = f64x4{0.0, 0.0, 0.0, 0.0};
-    __syncthreads();  // the previous pass is done with Wl
-    stage(0, 0);
-    loadb(0);
+    for (int b = 0; b < 8; ++b) acc[b] = f64x4{0.0, 0.0, 0.0, 0.0};
+    wstore(0);
+    if (nch > 1) wload(16);
     __syncthreads();
     for (int c = 0; c < nch; ++c) {
-      double cur[4][GP_TILES];
+      double cur[4];
 #pragma unroll
-      for (int ks = 0; ks < 4; ++ks)
-#pragma unroll
-        for (int t = 0; t < GP_TILES; ++t) cur[ks][t] = bd[ks][t];
-      if (c + 1 < nch) {
-        stage((c + 1) & 1, 16 * (c + 1));
-        loadb(16 * (c + 1));
-      }
+      for (int ks = 0; ks < 4; ++ks) cur[ks] = bd[ks];
+      if (c + 1 < nch) loadb(r0, 16 * (c + 1));
+      else if (more) loadb(rn, 0);
       const double* Wb = Wl[c & 1];
 #pragma unroll
       for (int ks = 0; ks < 4; ++ks)
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-          const double ra = Wb[(ks * 8 + b) * 64 + l];
-#pragma unroll
-          for (int t = 0; t < GP_TILES; ++t) acc[b][t] = mfma_f64(ra, cur[ks][t], acc[b][t]);
-        }
+        for (int b = 0; b < 8; ++b) acc[b] = mfma_f64(Wb[(ks * 8 + b) * 64 + l], cur[ks], acc[b]);
+      if (c + 1 < nch) {
+        wstore((c + 1) & 1);
+        if (c + 2 < nch) wload(16 * (c + 2));
+        else if (more) wload(0);
+      } else if (nch == 1 && more) {
+        wload(0);
+      }
       __syncthreads();
     }
-    // element (row 16 t + l%16, column 16 b + 4 r + l/16)
+    const bool row_in = r0 + c16 < rows;
 #pragma unroll
     for (int b = 0; b < 8; ++b)
 #pragma unroll
@@ -121,13 +133,10 @@ __global__ __launch_bounds__(GP_THREADS, 1) void gemm_panel_kernel(
         int64_t uc = r0 + (int64_t)(16 * b + 4 * r) * ldc, u0 = r0 + (int64_t)(16 * b + 4 * r) * ldc0;
         asm volatile("" : "+s"(uc), "+s"(u0));
         const bool in = row_in && 16 * b + 4 * r + g < nc;
-#pragma unroll
-        for (int t = 0; t < GP_TILES; ++t) {
-          if (in) {
-            double v = alpha * acc[b][t][r];
-            if (beta != 0.0) v = fma(beta, C0l[u0 + 16 * t], v);
-            Cl[uc + 16 * t] = v;
-          }
+        if (in) {
+          double v = alpha * acc[b][r];
+          if (beta != 0.0) v = fma(beta, __builtin_nontemporal_load(&C0l[u0]), v);
+          __builtin_nontemporal_store(v, &Cl[uc]);
         }
       }
   }
@@ -138,7 +147,8 @@ hipError_t launch_gemm_panel(bool tw, const double* Bs, int64_t ldb, int K, int 
                              double beta, const Ctrl* ctrl, int phase, hipStream_t st) {
   if (nc < 1 || nc > 128 || rows < 1 || K < 1) return hipErrorInvalidValue;
   const int64_t panels = ((int64_t)rows + GP_ROWS - 1) / GP_ROWS;
-  const dim3 grid((unsigned)(panels < 256 ? panels : 256)), block(GP_THREADS);
+  const int64_t cap = 512;
+  const dim3 grid((unsigned)(panels < cap ? panels : cap)), block(GP_THREADS);
   if (tw)
     hipLaunchKernelGGL(gemm_panel_kernel<true>, grid, block, 0, st, Bs, ldb, K, kvalid, W, ldw, C0, ldc0, C, ldc, rows,
                        nc, alpha, beta, ctrl, phase);
@@ -151,11 +161,15 @@ hipError_t launch_gemm_panel(bool tw, const double* Bs, int64_t ldb, int K, int 
 // ---------------------------------------------------------------------------
 // Gram blocks above the diagonal: partial sums over row chunks of
 // G_IJ = B_I^T B_J (128 x 128, I < J, column panels of B), one workgroup per
-// (chunk, pair). 64-row panels of B_I and B_J are staged in LDS
-// (column-major, 65-double stride); each of the 8 waves owns 2 x 4 of the
-// 64 tiles (A operand B_I^T from two column tiles, B operand B_J from four).
+// (chunk, pair). 32-row steps of B_I and B_J are staged in LDS
+// (column-major, odd 33-double stride: conflict-free stores and operand
+// reads), double-buffered, each step loaded into registers one step ahead;
+// each of the 8 waves owns 2 x 4 of the 64 tiles (A operand B_I^T from two
+// column tiles, B operand B_J from four).
 constexpr int GPR_THREADS = 512;
-constexpr int GPR_LD = 65;
+constexpr int GPR_ROWS = 32;                   // rows per step
+constexpr int GPR_LD = GPR_ROWS + 1;
+constexpr int GPR_EPT = 2 * GPR_ROWS * WD_PANEL / GPR_THREADS;  // staged entries per thread (both panels)
 
 // Pair pr of the blocks above the diagonal, row by row: (0,1), (0,2), ...,
 // (1,2), ...
@@ -166,18 +180,22 @@ __device__ __forceinline__ void pair_of(int pr, int n, int& I, int& J) {
   J = I + 1 + pr;
 }
 
-__global__ __launch_bounds__(GPR_THREADS, 1) void gram_pair_kernel(
-    const double* __restrict__ B, int m, int n, int64_t ldb, int chunks, int rows_per_chunk,
+// Grid: 8 npr ceil(chunks / 8) workgroups. Workgroups are dispatched to the
+// 8 XCDs round-robin; the npr pairs of one row chunk get ids 8 apart, so
+// they run on one XCD and share its L2 for the chunk's rows.
+__global__ __launch_bounds__(GPR_THREADS, 2) void gram_pair_kernel(
+    const double* __restrict__ B, int m, int n, int64_t ldb, int chunks, int rows_per_chunk, int npr,
     double* __restrict__ Gpart, const Ctrl* __restrict__ ctrl, int phase) {
-  __shared__ double Bi[128 * GPR_LD];
-  __shared__ double Bj[128 * GPR_LD];
+  __shared__ double Bt[2][2 * WD_PANEL * GPR_LD];
   if (skip_launch(ctrl, P_AUTO, phase)) return;
-  const int chunk = blockIdx.x, pr = blockIdx.y;
+  const int bid = blockIdx.x, xcd = bid & 7, rest = bid >> 3;
+  const int pr = rest % npr, chunk = (rest / npr) * 8 + xcd;
+  if (chunk >= chunks) return;
   int I, J;
   pair_of(pr, n, I, J);
   const int ci0 = WD_PANEL * I, cj0 = WD_PANEL * J;
   const int nci = min(WD_PANEL, n - ci0), ncj = min(WD_PANEL, n - cj0);
-  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, g = l >> 4, c16 = l & 15;
+  const int tid = threadIdx.x, w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63, g = l >> 4, c16 = l & 15;
   const int ta0 = 2 * (w % 4), tb0 = 4 * (w / 4);
   f64x4 acc[2][4];
 #pragma unroll
@@ -186,32 +204,58 @@ __global__ __launch_bounds__(GPR_THREADS, 1) void gram_pair_kernel(
     for (int b = 0; b < 4; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
   const int64_t rbeg = (int64_t)chunk * rows_per_chunk;
   const int64_t rend = min((int64_t)m, rbeg + rows_per_chunk);
-  for (int64_t p0 = rbeg; p0 < rend; p0 += 64) {
-    __syncthreads();
-    for (int e = tid; e < 64 * 128; e += GPR_THREADS) {
-      const int r = e % 64, c = e / 64;
-      const int64_t row = p0 + r;
-      const bool rin = row < rend;
-      Bi[c * GPR_LD + r] = (rin && c < nci) ? B[row + (int64_t)(ci0 + c) * ldb] : 0.0;
-      Bj[c * GPR_LD + r] = (rin && c < ncj) ? B[row + (int64_t)(cj0 + c) * ldb] : 0.0;
+  // staged entry q of this thread: row l % ROWS, column (panel-local)
+  // c = (64 q + tid) / ROWS over the 256 columns of both panels
+  constexpr int CPI = 64 / GPR_ROWS;  // columns per wave instruction
+  const int lr = l % GPR_ROWS, lc = l / GPR_ROWS;
+  double regs[GPR_EPT];
+  // a lane's base (row lr, column lc) plus wave-uniform offsets; entry q
+  // of a wave covers columns CW q + CPI w + (0..CPI-1) of the 256 (panel I
+  // then panel J), so its panel is uniform
+  constexpr int CW = GPR_THREADS / GPR_ROWS;
+  const double* Bl = B + lr + (int64_t)lc * ldb;
+  auto load = [&](int64_t p0) {
+    const bool rin = p0 + lr < rend;
+#pragma unroll
+    for (int q = 0; q < GPR_EPT; ++q) {
+      const int c0 = CW * q + CPI * w;          // uniform
+      const bool second = c0 >= WD_PANEL;       // uniform
+      const int cl0 = second ? c0 - WD_PANEL : c0;
+      int64_t u = p0 + (int64_t)((second ? cj0 : ci0) + cl0) * ldb;
+      asm volatile("" : "+s"(u));
+      const bool ok = rin && cl0 + lc < (second ? ncj : nci);
+      regs[q] = ok ? __builtin_nontemporal_load(&Bl[u]) : 0.0;
     }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < GPR_EPT; ++q) {
+      const int c = (GPR_THREADS / GPR_ROWS) * q + CPI * w + lc;
+      Bt[buf][c * GPR_LD + lr] = regs[q];
+    }
+  };
+  const int nsteps = (int)((rend - rbeg + GPR_ROWS - 1) / GPR_ROWS);
+  if (nsteps > 0) load(rbeg);
+  for (int s = 0; s < nsteps; ++s) {
+    const int buf = s & 1;
+    store(buf);
+    if (s + 1 < nsteps) load(rbeg + (int64_t)(s + 1) * GPR_ROWS);
     __syncthreads();
-#pragma unroll 4
-    for (int ks = 0; ks < 16; ++ks) {
-      const int k = 4 * ks + g;
+    const double* bi = Bt[buf] + c16 * GPR_LD + g;
+    const double* bj = Bt[buf] + (WD_PANEL + c16) * GPR_LD + g;
+#pragma unroll
+    for (int ks = 0; ks < GPR_ROWS / 4; ++ks) {
       double av[2], bv[4];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) av[a] = Bi[(16 * (ta0 + a) + c16) * GPR_LD + k];
+      for (int a = 0; a < 2; ++a) av[a] = bi[16 * (ta0 + a) * GPR_LD + 4 * ks];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) bv[b] = Bj[(16 * (tb0 + b) + c16) * GPR_LD + k];
+      for (int b = 0; b < 4; ++b) bv[b] = bj[16 * (tb0 + b) * GPR_LD + 4 * ks];
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = mfma_f64(av[a], bv[b], acc[a][b]);
     }
   }
-  // D[i][j] = (B_I^T B_J)[16 ta + i][16 tb + j]: lane l, register r holds
-  // D[4 r + l/16][l%16]
   double* out = Gpart + ((int64_t)pr * chunks + chunk) * (WD_PANEL * WD_PANEL);
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -245,7 +289,7 @@ __global__ void gram_pair_reduce_kernel(const double* __restrict__ Gpart, int ch
   G[gj + (int64_t)gi * ldg] = s;
 }
 
-constexpr int GPR_CHUNKS = 256;
+constexpr int GPR_CHUNKS = 128;
 
 int wide_panels(int n) { return (n + WD_PANEL - 1) / WD_PANEL; }
 int wide_pairs(int n) { const int np = wide_panels(n); return np * (np - 1) / 2; }
@@ -272,8 +316,9 @@ hipError_t launch_gram_wide(const double* B, int m, int n, int64_t ldb, double* 
   if (npr > 0) {
     const int rpc = (int)((((int64_t)m + GPR_CHUNKS - 1) / GPR_CHUNKS + 63) / 64 * 64);
     const int chunks = (int)(((int64_t)m + rpc - 1) / rpc);
-    hipLaunchKernelGGL(gram_pair_kernel, dim3(chunks, npr), dim3(GPR_THREADS), 0, st, B, m, n, ldb, chunks, rpc,
-                       Gpart_pairs, ctrl, phase);
+    const int chunks8 = (chunks + 7) / 8 * 8;
+    hipLaunchKernelGGL(gram_pair_kernel, dim3(chunks8 * npr), dim3(GPR_THREADS), 0, st, B, m, n, ldb, chunks, rpc,
+                       npr, Gpart_pairs, ctrl, phase);
     hipLaunchKernelGGL(gram_pair_reduce_kernel, dim3((WD_PANEL * WD_PANEL + 255) / 256, npr), dim3(256), 0, st,
                        (const double*)Gpart_pairs, chunks, n, G, ldg, ctrl, phase);
   }
@@ -734,52 +779,97 @@ hipError_t launch_trmm_wide(const double* R2, int64_t ld2, const double* R1, int
 // ---------------------------------------------------------------------------
 // The posterior check for n <= 512 (the n <= 128 kernel's estimate and
 // decision): sigma_max(Rc) and sigma_max(X) from POSTERIOR_STEPS power steps
-// on M^T M from the normalized all-ones vector, threads 0..511 for Rc and
-// 512..1023 for X (thread i forms y_i = (M x)_i, then z_i = (M^T y)_i).
-__global__ __launch_bounds__(1024) void posterior_wide_kernel(const double* __restrict__ Rc,
+// on M^T M from the normalized all-ones vector. Each step is two launches
+// over 16-row (16-column) blocks of both matrices, so that the n x n
+// matrices stream through many compute units: y = M x with x = z / ||z||
+// (every workgroup forms ||z|| itself, in one fixed order), then z = M^T y.
+// A last y = M x and a one-workgroup decision follow. Vectors live in ws:
+// z[2][WD_NMAX], then y[2][WD_NMAX].
+constexpr int PW_THREADS = 256;
+constexpr size_t POSTERIOR_WS_DOUBLES = 4 * WD_NMAX;
+
+__device__ __forceinline__ double block_sum_256(double v, double* red) {
+  v = wave_sum_dpp(v);
+  const int t = threadIdx.x;
+  __syncthreads();
+  if ((t & 63) == 0) red[t >> 6] = v;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// y = M x: workgroup (block, k), k = 0 for Rc and 1 for X; thread t takes
+// row 16 block + t % 16 and the columns j = t / 16 (mod 16), j >= row.
+__global__ __launch_bounds__(PW_THREADS) void power_mv_kernel(const double* __restrict__ Rc,
                                                               const double* __restrict__ X, int n, int64_t ld,
-                                                              Ctrl* __restrict__ ctrl, int phase,
-                                                              double* __restrict__ kappa_out) {
-  __shared__ double xs[2][WD_NMAX];
-  __shared__ double ys[2][WD_NMAX];
-  __shared__ double red[2][8];
+                                                              double* __restrict__ ws, int first,
+                                                              const Ctrl* __restrict__ ctrl, int phase) {
+  __shared__ double xs[WD_NMAX];
+  __shared__ double part[16][17];
+  __shared__ double red[4];
   if (skip_launch(ctrl, P_AUTO, phase)) return;
-  const int t = threadIdx.x, k = t >> 9, i = t & (WD_NMAX - 1), l = t & 63, wk = (t >> 6) & 7;
-  const bool broken = ctrl != nullptr && ctrl->pass_fail >= 0;
-  const double* M = k == 0 ? Rc : X;
-  double est[2] = {__builtin_inf(), __builtin_inf()};
-  if (!broken) {
-    xs[k][i] = i < n ? 1.0 / sqrt((double)n) : 0.0;
-    __syncthreads();
-    double y = 0.0;
-    for (int it = 0;; ++it) {
-      y = 0.0;
-      if (i < n)
-        for (int j = i; j < n; ++j) y = fma(M[i + (int64_t)j * ld], xs[k][j], y);
-      if (it == POSTERIOR_STEPS) break;
-      ys[k][i] = y;
-      __syncthreads();
-      double z = 0.0;
-      if (i < n)
-        for (int r = 0; r <= i; ++r) z = fma(M[r + (int64_t)i * ld], ys[k][r], z);
-      const double s2 = wave_sum_dpp(z * z);
-      if (l == 0) red[k][wk] = s2;
-      __syncthreads();
-      double nz2 = 0.0;
-      for (int q = 0; q < 8; ++q) nz2 += red[k][q];
-      xs[k][i] = z / sqrt(nz2);
-      __syncthreads();
-    }
-    const double q2 = wave_sum_dpp(y * y);
-    if (l == 0) red[k][wk] = q2;
-    __syncthreads();
-    for (int kk = 0; kk < 2; ++kk) {
-      double s = 0.0;
-      for (int q = 0; q < 8; ++q) s += red[kk][q];
-      est[kk] = sqrt(s);
-    }
+  const int k = blockIdx.y, blk = blockIdx.x, t = threadIdx.x;
+  const double* M = k ? X : Rc;
+  const double* z = ws + k * WD_NMAX;
+  double* y = ws + (2 + k) * WD_NMAX;
+  if (first) {
+    for (int i = t; i < n; i += PW_THREADS) xs[i] = 1.0 / sqrt((double)n);
+  } else {
+    double s = 0.0;
+    for (int i = t; i < n; i += PW_THREADS) s = fma(z[i], z[i], s);
+    const double nz = sqrt(block_sum_256(s, red));
+    for (int i = t; i < n; i += PW_THREADS) xs[i] = z[i] / nz;
+  }
+  __syncthreads();
+  const int r = t & 15, sl = t >> 4, i = 16 * blk + r;
+  double acc = 0.0;
+  if (i < n)
+    for (int j = sl; j < n; j += 16)
+      if (j >= i) acc = fma(M[i + (int64_t)j * ld], xs[j], acc);
+  part[sl][r] = acc;
+  __syncthreads();
+  if (t < 16 && 16 * blk + t < n) {
+    double v = 0.0;
+    for (int q = 0; q < 16; ++q) v += part[q][t];
+    y[16 * blk + t] = v;
+  }
+}
+
+// z = M^T y: thread t takes column 16 block + t / 16 and the rows
+// i = t % 16 (mod 16), i <= column; the 16 partial sums of a column are one
+// group of 16 lanes.
+__global__ __launch_bounds__(PW_THREADS) void power_tmv_kernel(const double* __restrict__ Rc,
+                                                               const double* __restrict__ X, int n, int64_t ld,
+                                                               double* __restrict__ ws,
+                                                               const Ctrl* __restrict__ ctrl, int phase) {
+  if (skip_launch(ctrl, P_AUTO, phase)) return;
+  const int k = blockIdx.y, blk = blockIdx.x, t = threadIdx.x;
+  const double* M = k ? X : Rc;
+  double* z = ws + k * WD_NMAX;
+  const double* y = ws + (2 + k) * WD_NMAX;
+  const int sl = t & 15, j = 16 * blk + (t >> 4);
+  double acc = 0.0;
+  if (j < n)
+    for (int i = sl; i <= j; i += 16) acc = fma(M[i + (int64_t)j * ld], y[i], acc);
+  acc = group_sum_dpp(acc, 16);
+  if (sl == 0 && j < n) z[j] = acc;
+}
+
+// ||M x|| after the last step, the estimate and the decision.
+__global__ __launch_bounds__(PW_THREADS) void posterior_decide_kernel(const double* __restrict__ ws, int n,
+                                                                      Ctrl* __restrict__ ctrl, int phase,
+                                                                      double* __restrict__ kappa_out) {
+  __shared__ double red[4];
+  if (skip_launch(ctrl, P_AUTO, phase)) return;
+  const int t = threadIdx.x;
+  double est[2];
+  for (int k = 0; k < 2; ++k) {
+    const double* y = ws + (2 + k) * WD_NMAX;
+    double s = 0.0;
+    for (int i = t; i < n; i += PW_THREADS) s = fma(y[i], y[i], s);
+    est[k] = sqrt(block_sum_256(s, red));
   }
   if (t != 0) return;
+  const bool broken = ctrl != nullptr && ctrl->pass_fail >= 0;
   const double kpow = est[0] * est[1];
   double kappa = __builtin_inf();
   if (!broken) {
@@ -805,10 +895,19 @@ __global__ __launch_bounds__(1024) void posterior_wide_kernel(const double* __re
   }
 }
 
-hipError_t launch_posterior_wide(const double* Rc, const double* X, int n, int64_t ld, Ctrl* ctrl, int phase,
-                                 double* kappa_out, hipStream_t st) {
-  if (n > WD_NMAX) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(posterior_wide_kernel, dim3(1), dim3(1024), 0, st, Rc, X, n, ld, ctrl, phase, kappa_out);
+size_t posterior_wide_ws_bytes() { return POSTERIOR_WS_DOUBLES * sizeof(double); }
+
+hipError_t launch_posterior_wide(const double* Rc, const double* X, int n, int64_t ld, double* ws, Ctrl* ctrl,
+                                 int phase, double* kappa_out, hipStream_t st) {
+  if (n > WD_NMAX || ws == nullptr) return hipErrorInvalidValue;
+  const dim3 grid((n + 15) / 16, 2), block(PW_THREADS);
+  for (int it = 0; it <= POSTERIOR_STEPS; ++it) {
+    hipLaunchKernelGGL(power_mv_kernel, grid, block, 0, st, Rc, X, n, ld, ws, it == 0 ? 1 : 0, (const Ctrl*)ctrl,
+                       phase);
+    if (it < POSTERIOR_STEPS)
+      hipLaunchKernelGGL(power_tmv_kernel, grid, block, 0, st, Rc, X, n, ld, ws, (const Ctrl*)ctrl, phase);
+  }
+  hipLaunchKernelGGL(posterior_decide_kernel, dim3(1), block, 0, st, (const double*)ws, n, ctrl, phase, kappa_out);
   return hipGetLastError();
 }
 

@@ -70,10 +70,16 @@ def test_step_entry_points_reject_shapes_synchronously(lib):
     lib.mrcqr_trmm.argtypes = [vp, i64, vp, i64, i64, vp, i64, vp]
     assert lib.mrcqr_trmm(fake, 600, fake, 600, 600, fake, 600, None) == 8
     assert lib.mrcqr_trmm(fake, 10, fake, 10, 11, fake, 11, None) == 1
-    lib.mrcqr_posterior_kappa.argtypes = [vp, vp, i64, i64, vp, vp]
-    assert lib.mrcqr_posterior_kappa(fake, fake, 600, 600, fake, None) == 8
-    assert lib.mrcqr_posterior_kappa(fake, None, 20, 20, fake, None) == 1
-    assert lib.mrcqr_posterior_kappa(fake, fake, 20, 19, fake, None) == 1
+    lib.mrcqr_posterior_kappa.argtypes = [vp, vp, i64, i64, vp, vp, vp]
+    assert lib.mrcqr_posterior_kappa(fake, fake, 600, 600, fake, None, None) == 8
+    assert lib.mrcqr_posterior_kappa(fake, None, 20, 20, fake, None, None) == 1
+    assert lib.mrcqr_posterior_kappa(fake, fake, 20, 19, fake, None, None) == 1
+    # n > 128 keeps its power vectors in a caller-owned workspace
+    lib.mrcqr_posterior_workspace_bytes.restype = ctypes.c_size_t
+    lib.mrcqr_posterior_workspace_bytes.argtypes = [i64]
+    assert lib.mrcqr_posterior_workspace_bytes(128) == 0
+    assert lib.mrcqr_posterior_workspace_bytes(300) >= 4 * 512 * 8
+    assert lib.mrcqr_posterior_kappa(fake, fake, 300, 300, fake, None, None) == 5
     # nothing cached in this process: releasing touches no device
     assert lib.mrcqr_release_cache() == 0
 
