@@ -193,32 +193,61 @@ def main() -> int:
     Rs = torch.from_numpy(np.ascontiguousarray(np.triu(R.cpu().numpy()).T)).cuda().t()
     X = M.empty_colmajor(m, n)
     tws = torch.empty(int(M.lib().mrcqr_trsm_workspace_bytes(n)), dtype=torch.uint8, device="cuda")
-    for _ in range(30):  # the clocks settle after the host-side accuracy work above
-        M.trsm(A, Rs, X, workspace=tws)
-    torch.cuda.synchronize()
-    # back-to-back launches between two events on the library's stream, in
-    # five rounds of `steps` launches (median round); one launch = the R
-    # staging kernel (a few us) + trsm_kernel
-    rounds = []
-    for _ in range(5):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(args.steps):
-            M.trsm(A, Rs, X, workspace=tws)
-        e1.record(stream)
+
+    def time_launches(fn) -> float:
+        for _ in range(30):  # the clocks settle after the host-side accuracy work above
+            fn()
         torch.cuda.synchronize()
-        rounds.append(e0.elapsed_time(e1) / args.steps)
-    trsm_ms = sorted(rounds)[len(rounds) // 2]
+        # back-to-back launches between two events on the library's stream, in
+        # five rounds of `steps` launches (median round)
+        rounds = []
+        for _ in range(5):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(args.steps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            rounds.append(e0.elapsed_time(e1) / args.steps)
+        return sorted(rounds)[len(rounds) // 2]
+
+    # one launch = the R staging kernel (a few us) + trsm_kernel (n <= 128),
+    # or the whole panel-blocked solve (n > 128)
+    trsm_ms = time_launches(lambda: M.trsm(A, Rs, X, workspace=tws))
     trsm_bytes = 2.0 * 8.0 * m * n  # read A, write X (algorithmic)
     achieved = trsm_bytes / (trsm_ms * 1e-3) / 1e9
     log(f"trsm kernel: {trsm_ms:.4f} ms/launch, {achieved:.1f} GB/s")
+    steps_rl = None
+    if n > 128:
+        # the column-panel path's three m x n steps, each a float64 MFMA
+        # contraction of m n^2 (solve) or m n (n + 1) (Gram, Q = B X)
+        # algorithmic flops over 16 m n (8 m n for the Gram) algorithmic bytes
+        Xi = M.tri_inverse(Rs)
+        gram_ms = time_launches(lambda: M.gram(X))
+        q_ms = time_launches(lambda: M.form_q(X, Xi, Q))
+        steps_rl = {}
+        for name, ms, fl, by, kern in (
+                ("solve B = A Rs^-1", trsm_ms, float(m) * n * n, 16.0 * m * n,
+                 "trsm_kernel<8> per 128-column panel + gemm_panel_kernel<false> updates"),
+                ("Gram G = B^T B", gram_ms, float(m) * n * (n + 1), 8.0 * m * n,
+                 "syrk_kernel per diagonal block + gram_pair_kernel + reductions"),
+                ("Q = B Rc^-1", q_ms, float(m) * n * (n + 1), 16.0 * m * n,
+                 "gemm_panel_kernel<false> per 128-column panel of Q")):
+            tf = fl / (ms * 1e-3) / 1e12
+            gbs = by / (ms * 1e-3) / 1e9
+            steps_rl[name] = {"ms": round(ms, 4), "kernels": kern, "algorithmic_flops": fl,
+                              "tflops": round(tf, 2), "mfma_frac": round(tf / FP64_PEAK_TFLOPS, 4),
+                              "algorithmic_bytes": by, "gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+            log(f"{name}: {ms:.4f} ms, {tf:.2f} TF/s ({tf / FP64_PEAK_TFLOPS:.3f} of fp64 MFMA), "
+                f"{gbs:.0f} GB/s ({gbs / HBM_PEAK_GBS:.3f} of HBM)")
 
     flop_2mn2 = 2.0 * m * n * n
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import mrcqr as OM, precision as P
-        mm = min(args.cpu_sample_rows, m)
+        # the oracle's cost grows like m n s = 2 m n^2: fewer rows for wider A
+        mm = min(args.cpu_sample_rows * (128 * 128) // (n * n) if n > 128 else args.cpu_sample_rows, m)
         log(f"cpu oracle on {mm} rows")
         sample = np.asfortranarray(A_h[:mm])
         t0 = time.perf_counter()
@@ -230,8 +259,24 @@ def main() -> int:
                          f"(n={n}, s={s}); {sec:.2f} s scaled by m/{mm}"}
         log(f"cpu oracle: {sec:.2f}s on {mm} rows -> {cpu['value']:.1f} ms/QR at full m")
 
+    if steps_rl is None:
+        roofline = {"kernel": "trsm_kernel<8> (X = A R^-1, float64, 8 column blocks of 16)", "bound": "hbm",
+                    "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": (round(trsm_traffic_bytes() / 1e9, 4) if (m, n) == (1 << 20, 128) and
+                                trsm_traffic_bytes() is not None else None),
+                    "traffic_unit": "GB per launch", "algorithmic_bytes_per_launch": trsm_bytes,
+                    "ms_per_launch": round(trsm_ms, 5)}
+    else:
+        # the dominant step (a sequence of launches; its time is the sum)
+        name, st_ = max(steps_rl.items(), key=lambda kv: kv[1]["ms"])
+        roofline = {"kernel": f"{name}: {st_['kernels']}", "bound": "mfma", "achieved": st_["tflops"],
+                    "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": st_["mfma_frac"], "traffic": None,
+                    "hbm_achieved_gbs": st_["gbs"], "hbm_frac": st_["hbm_frac"],
+                    "algorithmic_flops_per_launch": st_["algorithmic_flops"], "ms_per_launch": st_["ms"],
+                    "launch": "one call of the step (all its kernels)", "steps": steps_rl}
     out = {
-        "metric": METRIC,
+        "metric": METRIC if n == 128 else METRIC.replace("n=128", f"n={n}"),
         "value": round(ms16, 5),
         "unit": "ms/QR",
         "n_gpus": 1,
@@ -254,13 +299,7 @@ def main() -> int:
                            "fp64": round(flop_2mn2 / (ms64 * 1e-3) / 1e9, 2)},
         "fp64_mfma_roofline_frac_3mn2": round(3.0 * m * n * n / (ms16 * 1e-3) / (FP64_PEAK_TFLOPS * 1e12), 4),
         "accuracy": acc,
-        "roofline": {"kernel": "trsm_kernel<8> (X = A R^-1, float64, 8 column blocks of 16)", "bound": "hbm",
-                     "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": (round(trsm_traffic_bytes() / 1e9, 4) if (m, n) == (1 << 20, 128) and
-                                 trsm_traffic_bytes() is not None else None),
-                     "traffic_unit": "GB per launch", "algorithmic_bytes_per_launch": trsm_bytes,
-                     "ms_per_launch": round(trsm_ms, 5)},
+        "roofline": roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -80,7 +80,7 @@ struct SketchGeom { int chunks, rows_per_chunk; };
 SketchGeom sketch_geometry(int64_t m);
 // the column-panel path for 128 < n <= 512 (csrc/wide.hip)
 hipError_t launch_sketch_qr_wide(bool f64, double* Y, int s, int n, int64_t ldy, double* Rs, int64_t ldr,
-                                 double* tau, int* flags, double* kappa, Ctrl* ctrl, int slot, int phase,
+                                 double* tau, int* flags, double* Rt, double* kappa, Ctrl* ctrl, int slot, int phase,
                                  hipStream_t st);
 hipError_t launch_trsm_wide(const double* A, int m, int n, int64_t lda, const double* R, int64_t ldr, double* X,
                             int64_t ldx, void* ws, const Ctrl* ctrl, int phase, hipStream_t st);
@@ -88,7 +88,7 @@ size_t gram_pair_partial_bytes(int n);
 hipError_t launch_gram_wide(const double* B, int m, int n, int64_t ldb, double* Gpart_diag, double* Gpart_pairs,
                             double* G, int64_t ldg, const Ctrl* ctrl, int phase, hipStream_t st);
 hipError_t launch_cholesky_wide(double* G, int n, int64_t ldg, double* Rc, int64_t ldr, int32_t* fail,
-                                double* kappa, double* T, int32_t* fails, void* Tw, Ctrl* ctrl, int phase,
+                                double* kappa, double* T, int32_t* fails, double* Rt, void* Tw, Ctrl* ctrl, int phase,
                                 hipStream_t st);
 hipError_t launch_rc_tail_wide(const double* Rc, int n, int64_t ldc, const double* Rs, int64_t lds_, double* X,
                                int64_t ldx, double* R, int64_t ldr, const Ctrl* ctrl, int phase, hipStream_t st);
@@ -162,7 +162,8 @@ static void plan_layout(mrcqr_plan* p) {
   if (wide) {
     p->off_tau = take(n * sizeof(double));
     p->off_flags = take(sizeof(int));
-    p->off_Gpair = take(gram_pair_partial_bytes((int)n));
+    // also the row-major copies of Rs and Rc for their condition estimates
+    p->off_Gpair = take(std::max(gram_pair_partial_bytes((int)n), n * n * sizeof(double)));
     p->off_T = take(n * NSTEP * sizeof(double));
     p->off_fails = take(8 * sizeof(int32_t));
   }
@@ -199,9 +200,11 @@ static int execute(const mrcqr_plan* p, char* ws, const double* A, int64_t lda, 
     if (launch_sketch(pp, A, lda, m, n, S, s, seed, Ypart, Y, s, ctrl, phase, st, p->xform) != hipSuccess)
       return false;
     if (n > NSTEP)
+      // the Gram's pair partials are free until the Gram: Rs's row-major copy
       return launch_sketch_qr_wide(pp == P_FP64, Y, s, n, s, Rs, n, reinterpret_cast<double*>(ws + p->off_tau),
-                                   reinterpret_cast<int*>(ws + p->off_flags), nullptr, ctrl, pp, phase, st) ==
-             hipSuccess;
+                                   reinterpret_cast<int*>(ws + p->off_flags),
+                                   reinterpret_cast<double*>(ws + p->off_Gpair), nullptr, ctrl, pp, phase,
+                                   st) == hipSuccess;
     return launch_sketch_qr(pp == P_FP64, Y, s, n, s, Rs, n, nullptr, ctrl, pp, phase, st) == hipSuccess;
   };
   // Stage 2 and 3 of one pass; Q is formed in the pass's tail phase, which
@@ -212,7 +215,8 @@ static int execute(const mrcqr_plan* p, char* ws, const double* A, int64_t lda, 
              launch_gram_wide(B, m, n, ldb, Gpart, reinterpret_cast<double*>(ws + p->off_Gpair), G, n, ctrl, phase,
                               st) == hipSuccess &&
              launch_cholesky_wide(G, n, n, Rc, n, nullptr, nullptr, reinterpret_cast<double*>(ws + p->off_T),
-                                  reinterpret_cast<int32_t*>(ws + p->off_fails), Tw, ctrl, phase, st) == hipSuccess &&
+                                  reinterpret_cast<int32_t*>(ws + p->off_fails),
+                                  reinterpret_cast<double*>(ws + p->off_Gpair), Tw, ctrl, phase, st) == hipSuccess &&
              launch_rc_tail_wide(Rc, n, n, Rs, n, Rci, n, R, ldr, ctrl, phase, st) == hipSuccess &&
              launch_posterior_wide(Rc, Rci, n, n, reinterpret_cast<double*>(ws + p->off_T), ctrl, phase, nullptr,
                                    st) == hipSuccess &&

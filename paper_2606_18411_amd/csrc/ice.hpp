@@ -173,16 +173,66 @@ __device__ double ice_kappa_block(const double* R, int n, int si, int sj, bool r
   return eM / em;
 }
 
-// ice_kappa_block for n <= 512 (4 or 8 columns per lane; the kernels of
-// the column-panel path for n > 128 call it, so that the register budget of
-// the n <= 128 kernels stays as it is).
-__device__ double ice_kappa_block_wide(const double* R, int n, int si, int sj, bool run) {
+// ICE for n <= 512 on a row-major copy Rt of R (row j at Rt + j n, so a
+// wave reads each row contiguously), with the rows read DEPTH steps ahead
+// of the serial chain; the kernels of the column-panel path for n > 128
+// call it, so that the register budget of the n <= 128 kernels stays as
+// it is.
+template <int XPL, bool LARGEST>
+__device__ double ice_est_rows(const double* __restrict__ Rt, int n) {
+  constexpr int DEPTH = 4;
+  const int l = threadIdx.x & 63;
+  IceWave<XPL> ice;
+  ice.start(Rt, n, 1, LARGEST);
+  double ring[DEPTH][XPL], gring[DEPTH];
+  auto load = [&](int j, int slot) {
+#pragma unroll
+    for (int q = 0; q < XPL; ++q) {
+      const int k = l + 64 * q;
+      ring[slot][q] = (j < n && k > j && k < n) ? Rt[(int64_t)j * n + k] : 0.0;
+    }
+    gring[slot] = j < n ? Rt[(int64_t)j * n + j] : 0.0;
+  };
+#pragma unroll
+  for (int d = 0; d < DEPTH; ++d) load(1 + d, d);
+  for (int j0 = 1; j0 < n; j0 += DEPTH) {
+#pragma unroll
+    for (int d = 0; d < DEPTH; ++d) {
+      const int j = j0 + d;
+      if (j < n) {
+        double row[XPL];
+#pragma unroll
+        for (int q = 0; q < XPL; ++q) row[q] = ring[d][q];
+        const double gma = gring[d];
+        load(j + DEPTH, d);
+        const int jq = j >> 6;
+        double v = ice.b[0];
+#pragma unroll
+        for (int q = 1; q < XPL; ++q)
+          if (q == jq) v = ice.b[q];
+        const double alpha = readlane_t(v, j & 63);
+        ice.bad |= !isfinite(gma) || !isfinite(alpha);
+        double sn, cs;
+        ice_step(ice.es2, ice.F, alpha, gma, LARGEST, sn, cs);
+#pragma unroll
+        for (int q = 0; q < XPL; ++q) ice.b[q] = fma(sn, ice.b[q], cs * row[q]);
+      }
+    }
+  }
+  return ice.estimate();
+}
+
+// kappa estimate est_max / est_min of R (n <= 512) from its row-major copy
+// Rt: sigma_max on wave 0 and sigma_min on wave 1 (blockDim.x >= 128), run
+// only when RUN; every thread of the block calls it and receives the
+// result (NaN when not RUN, +inf for a singular or non-finite R).
+__device__ double ice_kappa_rows(const double* __restrict__ Rt, int n, bool run) {
   __shared__ double ice_res_w[2];
-  const int w = threadIdx.x >> 6;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (run && w < 2) {
     double est;
-    if (n <= 256) est = (w == 0) ? ice_est_wave<4, true>(R, n, si, sj) : ice_est_wave<4, false>(R, n, si, sj);
-    else est = (w == 0) ? ice_est_wave<8, true>(R, n, si, sj) : ice_est_wave<8, false>(R, n, si, sj);
+    if (n <= 256) est = (w == 0) ? ice_est_rows<4, true>(Rt, n) : ice_est_rows<4, false>(Rt, n);
+    else est = (w == 0) ? ice_est_rows<8, true>(Rt, n) : ice_est_rows<8, false>(Rt, n);
     if ((threadIdx.x & 63) == 0) ice_res_w[w] = est;
   }
   __syncthreads();

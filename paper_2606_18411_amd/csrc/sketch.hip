@@ -393,13 +393,26 @@ __device__ __forceinline__ void sketch_body(
     }
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin in linear order
+// (x fastest). With several sketch-row blocks, the blocks that read the
+// same rows and columns of A get linear ids 8 apart (one XCD, dispatched
+// together), so that A comes from HBM once and from that XCD's L2 for the
+// others; `remap` needs chunks x column blocks to be a multiple of 8.
 template <int P, int NTL, bool FULL>
 __global__ __launch_bounds__(64 * NTL) void sketch_kernel(
     const double* __restrict__ A, int64_t lda, int m, int n,
     const int32_t* __restrict__ S, int s, uint64_t seed, int rows_per_chunk,
-    typename SkT<P>::acc* __restrict__ Ypart, const Ctrl* __restrict__ ctrl, int phase, int xform) {
-  sketch_body<P, NTL, FULL>(A, lda, m, n, S, s, seed, rows_per_chunk, Ypart, ctrl, phase, blockIdx.x, blockIdx.y,
-                            blockIdx.z, xform);
+    typename SkT<P>::acc* __restrict__ Ypart, const Ctrl* __restrict__ ctrl, int phase, int xform, int remap) {
+  int chunk = blockIdx.x, cb = blockIdx.y, sb = blockIdx.z;
+  if (remap) {
+    const int L = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    const int q = L >> 3, nsb = gridDim.z;
+    const int pr = (q / nsb) * 8 + (L & 7);
+    sb = q % nsb;
+    chunk = pr % gridDim.x;
+    cb = pr / gridDim.x;
+  }
+  sketch_body<P, NTL, FULL>(A, lda, m, n, S, s, seed, rows_per_chunk, Ypart, ctrl, phase, chunk, cb, sb, xform);
 }
 
 // Grouped (members with n <= 128 and s <= 256: one column block and one
@@ -503,12 +516,13 @@ static void launch_sketch_v(int v, dim3 grid, hipStream_t st, const double* A, i
                             const int32_t* S, int s, uint64_t seed, int rows_per_chunk, typename SkT<P>::acc* Ypart,
                             const Ctrl* ctrl, int phase, int xform) {
   const dim3 block(64 * sketch_waves(v));
+  const int remap = (grid.z > 1 && (grid.x * grid.y) % 8 == 0) ? 1 : 0;
   switch (v) {
-    case 0: hipLaunchKernelGGL((sketch_kernel<P, 1, false>), grid, block, 0, st, A, lda, m, n, S, s, seed, rows_per_chunk, Ypart, ctrl, phase, xform); break;
-    case 1: hipLaunchKernelGGL((sketch_kernel<P, 2, false>), grid, block, 0, st, A, lda, m, n, S, s, seed, rows_per_chunk, Ypart, ctrl, phase, xform); break;
-    case 2: hipLaunchKernelGGL((sketch_kernel<P, 4, false>), grid, block, 0, st, A, lda, m, n, S, s, seed, rows_per_chunk, Ypart, ctrl, phase, xform); break;
-    case 3: hipLaunchKernelGGL((sketch_kernel<P, 8, false>), grid, block, 0, st, A, lda, m, n, S, s, seed, rows_per_chunk, Ypart, ctrl, phase, xform); break;
-    default: hipLaunchKernelGGL((sketch_kernel<P, 8, true>), grid, block, 0, st, A, lda, m, n, S, s, seed, rows_per_chunk, Ypart, ctrl, phase, xform); break;
+    case 0: hipLaunchKernelGGL((sketch_kernel<P, 1, false>), grid, block, 0, st, A, lda, m, n, S, s, seed, rows_per_chunk, Ypart, ctrl, phase, xform, remap); break;
+    case 1: hipLaunchKernelGGL((sketch_kernel<P, 2, false>), grid, block, 0, st, A, lda, m, n, S, s, seed, rows_per_chunk, Ypart, ctrl, phase, xform, remap); break;
+    case 2: hipLaunchKernelGGL((sketch_kernel<P, 4, false>), grid, block, 0, st, A, lda, m, n, S, s, seed, rows_per_chunk, Ypart, ctrl, phase, xform, remap); break;
+    case 3: hipLaunchKernelGGL((sketch_kernel<P, 8, false>), grid, block, 0, st, A, lda, m, n, S, s, seed, rows_per_chunk, Ypart, ctrl, phase, xform, remap); break;
+    default: hipLaunchKernelGGL((sketch_kernel<P, 8, true>), grid, block, 0, st, A, lda, m, n, S, s, seed, rows_per_chunk, Ypart, ctrl, phase, xform, remap); break;
   }
 }
 

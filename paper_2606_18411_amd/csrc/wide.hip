@@ -455,42 +455,105 @@ __global__ __launch_bounds__(1024) void hh_panel_kernel(double* __restrict__ Y, 
 
 // Apply the panel's reflectors (columns j0..j0+nb-1 of Y, below the
 // diagonal, tau) to column c of Y (c >= j0 + nb), rows j0..s-1, in order;
-// one wave per column, arithmetic in T.
+// one wave per column, arithmetic in T. A workgroup of 16 waves (16
+// columns) stages the reflectors in LDS, HH_KB of them at a time (128 KB),
+// so that the serial chain of a column reads no global memory.
 template <typename T, int RPL>
-__global__ __launch_bounds__(256) void hh_apply_kernel(double* __restrict__ Y, int s, int n, int64_t ldy, int j0,
-                                                       int nb, const double* __restrict__ tau,
-                                                       const Ctrl* __restrict__ ctrl, int slot, int phase) {
+__global__ __launch_bounds__(1024) void hh_apply_kernel(double* __restrict__ Y, int s, int n, int64_t ldy, int j0,
+                                                        int nb, const double* __restrict__ tau,
+                                                        const Ctrl* __restrict__ ctrl, int slot, int phase) {
+  constexpr int LEN = 64 * RPL;
+  constexpr int HH_KB = (128 * 1024) / (LEN * (int)sizeof(T));
+  __shared__ T vs[HH_KB][LEN];
   if (skip_launch(ctrl, slot, phase)) return;
-  const int l = threadIdx.x & 63;
-  const int c = j0 + nb + blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (c >= n) return;
+  const int tid = threadIdx.x, l = tid & 63;
+  const int c = j0 + nb + blockIdx.x * 16 + (tid >> 6);
+  const bool have = c < n;
   const int sp = s - j0;
   T y[RPL];
 #pragma unroll
   for (int i = 0; i < RPL; ++i) {
     const int r = l + 64 * i;
-    y[i] = (r < sp) ? (T)Y[(j0 + r) + (int64_t)c * ldy] : (T)0;
+    y[i] = (have && r < sp) ? (T)Y[(j0 + r) + (int64_t)c * ldy] : (T)0;
   }
-  for (int k = 0; k < nb; ++k) {
-    const double* vk = Y + j0 + (int64_t)(j0 + k) * ldy;
-    T v[RPL];
-#pragma unroll
-    for (int i = 0; i < RPL; ++i) {
-      const int r = l + 64 * i;
-      v[i] = (r > k && r < sp) ? (T)vk[r] : (r == k ? (T)1 : (T)0);
+  for (int k0 = 0; k0 < nb; k0 += HH_KB) {
+    const int kb = min(HH_KB, nb - k0);
+    __syncthreads();  // the previous stage's reflectors are applied
+    for (int e = tid; e < kb * LEN; e += 1024) {
+      const int kk = e / LEN, r = e % LEN, k = k0 + kk;
+      const double* vk = Y + j0 + (int64_t)(j0 + k) * ldy;
+      vs[kk][r] = (r > k && r < sp) ? (T)vk[r] : (r == k ? (T)1 : (T)0);
     }
-    T dp = (T)0;
+    __syncthreads();
+    if (have) {
+      for (int kk = 0; kk < kb; ++kk) {
+        T dp = (T)0;
 #pragma unroll
-    for (int i = 0; i < RPL; ++i) dp += v[i] * y[i];
-    const T f = (T)tau[j0 + k] * wave_sum_dpp(dp);
+        for (int i = 0; i < RPL; ++i) dp += vs[kk][l + 64 * i] * y[i];
+        const T f = (T)tau[j0 + k0 + kk] * wave_sum_dpp(dp);
 #pragma unroll
-    for (int i = 0; i < RPL; ++i) y[i] -= f * v[i];
+        for (int i = 0; i < RPL; ++i) y[i] -= f * vs[kk][l + 64 * i];
+      }
+    }
   }
+  if (!have) return;
 #pragma unroll
   for (int i = 0; i < RPL; ++i) {
     const int r = l + 64 * i;
     if (r < sp) Y[(j0 + r) + (int64_t)c * ldy] = (double)y[i];
   }
+}
+
+// Upper triangle of an n x n matrix into dst (below it zero; everything
+// zero when one of the np pivots in fails[] is set) and into a row-major
+// copy Rt (row r at Rt + r n) for the condition estimate, by 32 x 32 tiles
+// transposed through LDS. flip: row r is multiplied by the sign of
+// src(r, r) (R with a positive diagonal from a Householder factor), and a
+// diagonal entry that is not positive and finite or an off-diagonal entry
+// that is not finite sets bit 4 of *flags.
+__global__ __launch_bounds__(256) void upper_copy_kernel(const double* src, int64_t lds, double* dst, int64_t ldd,
+                                                         double* __restrict__ Rt, int n, int flip,
+                                                         const int32_t* __restrict__ fails, int np,
+                                                         int* __restrict__ flags, const Ctrl* __restrict__ ctrl,
+                                                         int slot, int phase) {
+  __shared__ double tile[32][33];
+  if (skip_launch(ctrl, slot, phase)) return;
+  bool zero_all = false;
+  if (fails)
+    for (int P = 0; P < np; ++P) zero_all = zero_all || fails[P] >= 0;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int r0 = blockIdx.x * 32, c0 = blockIdx.y * 32;
+  bool bad = false;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int r = r0 + tx, c = c0 + ty + 8 * k;
+    double v = 0.0;
+    if (r < n && c < n && r <= c && !zero_all) {
+      v = src[r + (int64_t)c * lds];
+      if (flip) {
+        v = (src[r + (int64_t)r * lds] < 0.0 ? -1.0 : 1.0) * v;
+        if (r == c && !(v > 0.0 && isfinite(v))) bad = true;
+        if (r < c && !isfinite(v)) bad = true;
+      }
+    }
+    if (r < n && c < n) dst[r + (int64_t)c * ldd] = v;
+    tile[ty + 8 * k][tx] = v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int r = r0 + ty + 8 * k, c = c0 + tx;
+    if (r < n && c < n) Rt[(int64_t)r * n + c] = tile[tx][ty + 8 * k];
+  }
+  if (flags && bad) atomicOr(flags, 4);
+}
+
+static void launch_upper_copy(const double* src, int64_t lds, double* dst, int64_t ldd, double* Rt, int n, bool flip,
+                              const int32_t* fails, int np, int* flags, const Ctrl* ctrl, int slot, int phase,
+                              hipStream_t st) {
+  const dim3 grid((n + 31) / 32, (n + 31) / 32), block(256);
+  hipLaunchKernelGGL(upper_copy_kernel, grid, block, 0, st, src, lds, dst, ldd, Rt, n, flip ? 1 : 0, fails, np, flags,
+                     ctrl, slot, phase);
 }
 
 // Clear the flags word of the sketch QR (a small fill kernel, so the
@@ -500,34 +563,19 @@ __global__ void wide_flags_clear_kernel(int* flags, const Ctrl* __restrict__ ctr
   if (threadIdx.x == 0) *flags = 0;
 }
 
-// R from the factored Y with diag(R) > 0 (rows with a negative pivot
-// flipped), the singular / non-finite checks and the condition estimate of
-// Rs with the AUTO escalation (the epilogue of the n <= 128 sketch QR).
-__global__ __launch_bounds__(256) void hh_finish_kernel(const double* __restrict__ Y, int n, int64_t ldy,
-                                                         double* __restrict__ Rs, int64_t ldr,
+// The checks and the condition estimate of Rs with the AUTO escalation (the
+// epilogue of the n <= 128 sketch QR), after upper_copy_kernel has written
+// Rs (diag(Rs) > 0), its row-major copy Rt and the flags.
+__global__ __launch_bounds__(256) void hh_finish_kernel(const double* __restrict__ Rt, int n,
                                                          const int* __restrict__ flags,
                                                          double* __restrict__ kappa_out, Ctrl* __restrict__ ctrl,
                                                          int slot, int phase, int want_kappa) {
-  __shared__ int bad_sh;
   if (skip_launch(ctrl, slot, phase)) return;
-  if (threadIdx.x == 0) bad_sh = 0;
-  __syncthreads();
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-    const int r = e % n, c = e / n;
-    double v = 0.0;
-    if (r <= c) {
-      const double d = Y[r + (int64_t)r * ldy];
-      v = (d < 0.0 ? -1.0 : 1.0) * Y[r + (int64_t)c * ldy];
-      if (r == c && !(v > 0.0 && isfinite(v))) bad_sh = 1;
-      if (r < c && !isfinite(v)) bad_sh = 1;
-    }
-    Rs[r + (int64_t)c * ldr] = v;
-  }
-  __syncthreads();
-  const bool nonfinite = (*flags & 2) != 0;
-  const bool bad = bad_sh != 0 || nonfinite;
+  const int fl = *flags;
+  const bool nonfinite = (fl & 2) != 0;
+  const bool bad = (fl & 4) != 0 || nonfinite;
   const bool auto_here = ctrl != nullptr && ctrl->auto_mode;
-  double kappa = ice_kappa_block_wide(Rs, n, 1, (int)ldr, !bad && (auto_here || want_kappa));
+  double kappa = ice_kappa_rows(Rt, n, !bad && (auto_here || want_kappa));
   if (bad) kappa = __builtin_inf();
   if (threadIdx.x != 0) return;
   if (kappa_out) *kappa_out = kappa;
@@ -557,15 +605,15 @@ static hipError_t hh_panels(double* Y, int s, int n, int64_t ldy, double* tau, i
                        ctrl, slot, phase);
     const int rest = n - j0 - nb;
     if (rest > 0)
-      hipLaunchKernelGGL((hh_apply_kernel<T, RPL>), dim3((rest + 3) / 4), dim3(256), 0, st, Y, s, n, ldy, j0, nb,
-                         (const double*)tau, ctrl, slot, phase);
+      hipLaunchKernelGGL((hh_apply_kernel<T, RPL>), dim3((rest + 15) / 16), dim3(1024), 0, st, Y, s, n, ldy, j0,
+                         nb, (const double*)tau, ctrl, slot, phase);
   }
   return hipGetLastError();
 }
 
 // The sketch QR for n > 128: Y (s x n, ld ldy) is overwritten.
 hipError_t launch_sketch_qr_wide(bool f64, double* Y, int s, int n, int64_t ldy, double* Rs, int64_t ldr,
-                                 double* tau, int* flags, double* kappa, Ctrl* ctrl, int slot, int phase,
+                                 double* tau, int* flags, double* Rt, double* kappa, Ctrl* ctrl, int slot, int phase,
                                  hipStream_t st) {
   if (n > WD_NMAX || s > 16 * 64 || s < n) return hipErrorInvalidValue;
   hipLaunchKernelGGL(wide_flags_clear_kernel, dim3(1), dim3(64), 0, st, flags, (const Ctrl*)ctrl, slot, phase);
@@ -579,8 +627,9 @@ hipError_t launch_sketch_qr_wide(bool f64, double* Y, int s, int n, int64_t ldy,
     else e = hh_panels<float, 16>(Y, s, n, ldy, tau, flags, ctrl, slot, phase, st);
   }
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(hh_finish_kernel, dim3(1), dim3(256), 0, st, (const double*)Y, n, ldy, Rs, ldr,
-                     (const int*)flags, kappa, ctrl, slot, phase, kappa != nullptr ? 1 : 0);
+  launch_upper_copy(Y, ldy, Rs, ldr, Rt, n, true, nullptr, 0, flags, ctrl, slot, phase, st);
+  hipLaunchKernelGGL(hh_finish_kernel, dim3(1), dim3(256), 0, st, (const double*)Rt, n, (const int*)flags, kappa,
+                     ctrl, slot, phase, kappa != nullptr ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -642,10 +691,11 @@ __global__ void wide_transpose_kernel(const double* __restrict__ T, int64_t ldt,
 }
 
 // The factorization's outcome: the first failing pivot over the panels (in
-// the whole matrix's numbering), the lower triangle cleared, and the ICE of
-// Rc, into the control block as the n <= 128 Cholesky kernel leaves them.
+// the whole matrix's numbering) and the ICE of Rc (from its row-major copy
+// Rt; upper_copy_kernel has cleared the lower triangle), into the control
+// block as the n <= 128 Cholesky kernel leaves them.
 __global__ __launch_bounds__(256) void chol_wide_finish_kernel(const int32_t* __restrict__ fails, int np, int n,
-                                                               double* __restrict__ Rc, int64_t ldr,
+                                                               const double* __restrict__ Rt,
                                                                int32_t* __restrict__ fail_out,
                                                                double* __restrict__ kappa_out,
                                                                Ctrl* __restrict__ ctrl, int phase) {
@@ -653,12 +703,7 @@ __global__ __launch_bounds__(256) void chol_wide_finish_kernel(const int32_t* __
   int f = -1;
   for (int P = 0; P < np; ++P)
     if (fails[P] >= 0) { f = WD_PANEL * P + fails[P]; break; }
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-    const int r = e % n, c = e / n;
-    if (r > c || f >= 0) Rc[r + (int64_t)c * ldr] = 0.0;
-  }
-  __syncthreads();
-  double kappa = ice_kappa_block_wide(Rc, n, 1, (int)ldr, f < 0);
+  double kappa = ice_kappa_rows(Rt, n, f < 0);
   if (f >= 0) kappa = __builtin_inf();
   if (threadIdx.x != 0) return;
   if (fail_out) *fail_out = f;
@@ -670,10 +715,10 @@ __global__ __launch_bounds__(256) void chol_wide_finish_kernel(const int32_t* __
 }
 
 // G = Rc^T Rc for n <= 512, right-looking over 128-column panels. G is
-// overwritten (trailing updates); T (n x 128, ld n) and fails (np ints) are
-// scratch; Tw the solve's staging workspace.
+// overwritten (trailing updates); T (n x 128, ld n), fails (np ints) and Rt
+// (n x n) are scratch; Tw the solve's staging workspace.
 hipError_t launch_cholesky_wide(double* G, int n, int64_t ldg, double* Rc, int64_t ldr, int32_t* fail,
-                                double* kappa, double* T, int32_t* fails, void* Tw, Ctrl* ctrl, int phase,
+                                double* kappa, double* T, int32_t* fails, double* Rt, void* Tw, Ctrl* ctrl, int phase,
                                 hipStream_t st) {
   const int np = wide_panels(n);
   for (int P = 0; P < np; ++P) {
@@ -697,20 +742,23 @@ hipError_t launch_cholesky_wide(double* G, int n, int64_t ldg, double* Rc, int64
       if (e != hipSuccess) return e;
     }
   }
-  hipLaunchKernelGGL(chol_wide_finish_kernel, dim3(1), dim3(256), 0, st, (const int32_t*)fails, np, n, Rc, ldr, fail,
-                     kappa, ctrl, phase);
+  launch_upper_copy(Rc, ldr, Rc, ldr, Rt, n, false, fails, np, nullptr, ctrl, P_AUTO, phase, st);
+  hipLaunchKernelGGL(chol_wide_finish_kernel, dim3(1), dim3(256), 0, st, (const int32_t*)fails, np, n,
+                     (const double*)Rt, fail, kappa, ctrl, phase);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // X = R^{-1} (R upper triangular, n <= 512): one wave per column j, lane l
 // holding rows l + 64 q; x_i is formed on the lane holding row i and read
-// by the others (back substitution in column order).
+// by the others (back substitution in column order). The columns of R are
+// read TI_DEPTH steps ahead of the serial chain.
 __global__ __launch_bounds__(64) void trinv_wide_kernel(const double* __restrict__ R, int n, int64_t ldr,
                                                         double* __restrict__ X, int64_t ldx,
                                                         const Ctrl* __restrict__ ctrl, int phase) {
   if (skip_launch(ctrl, P_AUTO, phase)) return;
   constexpr int Q = WD_NMAX / 64;
+  constexpr int TI_DEPTH = 4;
   const int j = blockIdx.x, l = threadIdx.x;
   double sv[Q], rinv[Q];
 #pragma unroll
@@ -720,18 +768,39 @@ __global__ __launch_bounds__(64) void trinv_wide_kernel(const double* __restrict
     rinv[q] = 1.0 / R[rc + (int64_t)rc * ldr];
     sv[q] = (r == j) ? 1.0 : 0.0;
   }
-  for (int i = j; i >= 0; --i) {
-    const int qi = i >> 6;
-    double own = 0.0;
-#pragma unroll
-    for (int q = 0; q < Q; ++q)
-      if (q == qi) own = sv[q] * rinv[q];
-    const double x = readlane_t(own, i & 63);
+  // ring[d]: entries r < i of column i of R
+  double ring[TI_DEPTH][Q];
+  auto load = [&](int i, int slot) {
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int r = l + 64 * q;
-      if (r == i) sv[q] = x;
-      else if (r < i) sv[q] = fma(-R[r + (int64_t)i * ldr], x, sv[q]);
+      ring[slot][q] = (i >= 0 && r < i) ? R[r + (int64_t)i * ldr] : 0.0;
+    }
+  };
+#pragma unroll
+  for (int d = 0; d < TI_DEPTH; ++d) load(j - d, d);
+  for (int i0 = j; i0 >= 0; i0 -= TI_DEPTH) {
+#pragma unroll
+    for (int d = 0; d < TI_DEPTH; ++d) {
+      const int i = i0 - d;
+      if (i >= 0) {
+        double col[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) col[q] = ring[d][q];
+        load(i - TI_DEPTH, d);
+        const int qi = i >> 6;
+        double own = 0.0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+          if (q == qi) own = sv[q] * rinv[q];
+        const double x = readlane_t(own, i & 63);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          const int r = l + 64 * q;
+          if (r == i) sv[q] = x;
+          else if (r < i) sv[q] = fma(-col[q], x, sv[q]);
+        }
+      }
     }
   }
 #pragma unroll

@@ -9,6 +9,7 @@ import pytest
 
 import workloads as W
 from oracle import cholqr as CQ, condest as CE, householder as HH, metrics as MT, mrcqr as OM, precision as P
+from oracle import rng, sketch as SK
 from gpu_common import require_gpu, to_dev, to_host, progress, torch, _chunked_gram_dev
 
 pytestmark = pytest.mark.gpu
@@ -31,6 +32,28 @@ def _problem(m, n, kappa, seed):
         Qt, Rt = HH.householder_qr(sig[:, None] * V.T)
         _REF[key] = (A, U, Qt, Rt)
     return _REF[key]
+
+
+U32 = 2.0 ** -24
+SKETCH_TOL = {P.FP64: 2e-12, P.FP32: 200 * U32, P.FP16: 2e-5, P.BF16: 1.6e-4}
+
+
+# m = 2^14 gives 256 row chunks, so the sketch-row blocks (s / 256 of them)
+# that share rows of A run on one XCD (the remapped grid); m = 5003 keeps
+# the plain grid
+@pytest.mark.parametrize("prec", [P.FP64, P.FP32, P.FP16, P.BF16])
+@pytest.mark.parametrize("m,n", [(16384, 512), (16384, 256), (5003, 300)])
+def test_wide_sketch_matches_definition(M, prec, m, n):
+    s, seed = 2 * n, 3 + n
+    progress(f"wide sketch {P.NAMES[prec]} m={m} n={n} s={s}")
+    A = W.test_matrix(m, n, 1e4, 2)
+    S = rng.sample_rows(seed, m, s)
+    d = rng.signs(seed, m)
+    Y = to_host(M.sketch(to_dev(A), torch.from_numpy(S.astype(np.int32)).cuda(), seed, P.NAMES[prec]))
+    Yo = SK.sketch(A, S, d, prec)
+    bound = SK.sketch_abs_bound(A, S, d, prec)
+    err = np.abs(Y - Yo) - (SKETCH_TOL[prec] * bound + (U32 * np.abs(Yo) if prec != P.FP64 else 0))
+    assert np.max(err) <= 0, f"max excess {np.max(err):.3e}"
 
 
 @pytest.mark.parametrize("m,n,kappa", [(3001, 256, 1e6), (1200, 200, 1e4), (5003, 512, 1e8)])
