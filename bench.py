@@ -246,8 +246,8 @@ def main() -> int:
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import mrcqr as OM, precision as P
-        # the oracle's cost grows like m n s = 2 m n^2: fewer rows for wider A
-        mm = min(args.cpu_sample_rows * (128 * 128) // (n * n) if n > 128 else args.cpu_sample_rows, m)
+        # fewer rows for wider A (about 10 s of oracle work)
+        mm = min(args.cpu_sample_rows * 128 // n if n > 128 else args.cpu_sample_rows, m)
         log(f"cpu oracle on {mm} rows")
         sample = np.asfortranarray(A_h[:mm])
         t0 = time.perf_counter()

@@ -36,10 +36,19 @@
  *     after synchronizing the stream;
  *   - results are deterministic: the same inputs, seed and device give
  *     bitwise-identical outputs (no floating-point atomics).
- * Limits of this library: 1 <= n <= 128, n <= s <= m, m < 2^28, and the
- * sketch must fit the one-workgroup Householder QR: s <= 2048 for n <= 16,
- * s <= 1024 for n <= 32, s <= 512 for n <= 64, s <= 256 for n <= 128
- * (the default s = 2n always fits).
+ * Limits of this library: n <= s <= m, m < 2^28, and
+ *   - the factorization (mrcqr_factor, the plan API, the no-allocation
+ *     entry point) and the steps mrcqr_sketch, mrcqr_trsm, mrcqr_gram,
+ *     mrcqr_tri_inverse, mrcqr_form_q, mrcqr_trmm and mrcqr_posterior_kappa
+ *     take 1 <= n <= 512; for 128 < n <= 512 they run a column-panel path
+ *     (128-column panels of the solve, the Gram, the Cholesky and the
+ *     product; a blocked Householder QR of the sketch, s <= 1024);
+ *   - for n <= 128 the sketch must fit the one-workgroup Householder QR:
+ *     s <= 2048 for n <= 16, s <= 1024 for n <= 32, s <= 512 for n <= 64,
+ *     s <= 256 for n <= 128 (the default s = 2n always fits);
+ *   - batches, CholQR2, mrcqr_sketch_qr, mrcqr_cholesky, mrcqr_condest and
+ *     the estimators take n <= 128;
+ *   - larger shapes return MRCQR_ERR_UNSUPPORTED.
  */
 #ifndef MRCQR_H
 #define MRCQR_H
@@ -311,7 +320,9 @@ int mrcqr_sketch_qr(const double* Y, int64_t s, int64_t n, int64_t ldy, int qr_p
  * substitution over column blocks of 16: X_J = (A_J - X_{<J} R_{<J,J})
  * inv(R_JJ). No inverse of R is formed (Section "Algorithm Description");
  * only the 16 x 16 diagonal blocks are inverted (by substitution), as GPU
- * triangular solves do. X must not overlap A. Needs
+ * triangular solves do. For n > 128 the columns are taken in panels of
+ * 128: X_P = (A_P - X_{<P} R_{<P,P}) R_PP^{-1}, the update written into X_P
+ * and solved there. X must not overlap A. Needs
  * mrcqr_trsm_workspace_bytes(n) bytes of device workspace (R staged in
  * operand order; about 75 KB at n = 128). */
 size_t mrcqr_trsm_workspace_bytes(int64_t n);
@@ -320,7 +331,9 @@ int mrcqr_trsm(const double* A, int64_t m, int64_t n, int64_t lda,
                void* workspace, size_t workspace_bytes, void* stream);
 
 /* Algorithm 1 step 1: G = B^T B (n x n, both triangles written). Needs
- * mrcqr_gram_workspace_bytes(m, n) bytes of device workspace. */
+ * mrcqr_gram_workspace_bytes(m, n) bytes of device workspace (per-row-chunk
+ * partial sums, summed in a fixed order; for n > 128 also those of the
+ * 128 x 128 blocks above the diagonal). */
 size_t mrcqr_gram_workspace_bytes(int64_t m, int64_t n);
 int mrcqr_gram(const double* B, int64_t m, int64_t n, int64_t ldb,
                double* G, int64_t ldg, void* workspace, size_t workspace_bytes,
@@ -333,7 +346,7 @@ int mrcqr_cholesky(const double* G, int64_t n, int64_t ldg, double* Rc, int64_t 
                    int32_t* fail_dev, double* kappa_dev, void* stream);
 
 /* Algorithm 1 step 3, first half: X = R^{-1} for an upper-triangular
- * n x n R (n <= 128) by column-wise back substitution, x_i = (e_j -
+ * n x n R (n <= 512) by column-wise back substitution, x_i = (e_j -
  * sum_{k>i} r_ik x_k)_i / r_ii. Only the upper triangle of R is read; the
  * strict lower triangle of X is written as zeros. X must not overlap R. A
  * zero or non-finite diagonal entry gives non-finite columns (no status;
@@ -348,7 +361,7 @@ int mrcqr_tri_inverse(const double* R, int64_t n, int64_t ldr, double* X, int64_
 int mrcqr_form_q(const double* B, int64_t m, int64_t n, int64_t ldb, const double* X, int64_t ldx,
                  double* Q, int64_t ldq, void* stream);
 
-/* Stage 3: R = R2 R1 for upper-triangular n x n factors (n <= 128). */
+/* Stage 3: R = R2 R1 for upper-triangular n x n factors (n <= 512). */
 int mrcqr_trmm(const double* R2, int64_t ld2, const double* R1, int64_t ld1,
                int64_t n, double* R, int64_t ldr, void* stream);
 

@@ -289,13 +289,18 @@ __global__ void gram_pair_reduce_kernel(const double* __restrict__ Gpart, int ch
   G[gj + (int64_t)gi * ldg] = s;
 }
 
-constexpr int GPR_CHUNKS = 128;
+// Row chunks per pair: about 768 workgroups over all pairs (three per
+// compute unit), at most 512 chunks.
+static int gpr_max_chunks(int npr) {
+  const int c = (768 / (npr > 0 ? npr : 1) + 7) / 8 * 8;
+  return c > 512 ? 512 : c;
+}
 
 int wide_panels(int n) { return (n + WD_PANEL - 1) / WD_PANEL; }
 int wide_pairs(int n) { const int np = wide_panels(n); return np * (np - 1) / 2; }
 
 size_t gram_pair_partial_bytes(int n) {
-  return (size_t)wide_pairs(n) * GPR_CHUNKS * WD_PANEL * WD_PANEL * sizeof(double) + 256;
+  return (size_t)wide_pairs(n) * gpr_max_chunks(wide_pairs(n)) * WD_PANEL * WD_PANEL * sizeof(double) + 256;
 }
 
 hipError_t launch_gram(const double* B, int m, int n, int64_t ldb, double* Gpart, double* G, int64_t ldg,
@@ -314,7 +319,8 @@ hipError_t launch_gram_wide(const double* B, int m, int n, int64_t ldb, double* 
   }
   const int npr = wide_pairs(n);
   if (npr > 0) {
-    const int rpc = (int)((((int64_t)m + GPR_CHUNKS - 1) / GPR_CHUNKS + 63) / 64 * 64);
+    const int maxc = gpr_max_chunks(npr);
+    const int rpc = (int)((((int64_t)m + maxc - 1) / maxc + 63) / 64 * 64);
     const int chunks = (int)(((int64_t)m + rpc - 1) / rpc);
     const int chunks8 = (chunks + 7) / 8 * 8;
     hipLaunchKernelGGL(gram_pair_kernel, dim3(chunks8 * npr), dim3(GPR_THREADS), 0, st, B, m, n, ldb, chunks, rpc,
