@@ -148,6 +148,18 @@ __device__ __forceinline__ bool skip_launch(const Ctrl* ctrl, int slot_prec, int
   return slot_prec != P_AUTO && ctrl->cur_prec != slot_prec;
 }
 
+// An element of a matrix, or zero where the element lies outside it, by an
+// unconditional global load from either the element or a zero word: with
+// no branch around the load and no select on its value, the compiler keeps
+// counting the loads in flight across loop iterations (loads read several
+// steps ahead of a serial chain stay in flight) instead of waiting for all
+// of them at a branch.
+typedef const __attribute__((address_space(1))) double gdouble;
+static __device__ const double k_zero_word[1] = {0.0};
+__device__ __forceinline__ double load_or_zero(const double* p, bool in) {
+  return *(in ? (gdouble*)p : (gdouble*)k_zero_word);
+}
+
 // Raise a kernel's dynamic LDS limit to `bytes` when above the default
 // 64 KiB; the call's own error state is cleared so that a later
 // hipGetLastError() reports only launch failures.

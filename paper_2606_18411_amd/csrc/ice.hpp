@@ -189,36 +189,42 @@ __device__ double ice_est_rows(const double* __restrict__ Rt, int n) {
 #pragma unroll
     for (int q = 0; q < XPL; ++q) {
       const int k = l + 64 * q;
-      ring[slot][q] = (j < n && k > j && k < n) ? Rt[(int64_t)j * n + k] : 0.0;
+      const bool in = j < n && k > j && k < n;
+      ring[slot][q] = load_or_zero(Rt + (in ? (int64_t)j * n + k : 0), in);
     }
-    gring[slot] = j < n ? Rt[(int64_t)j * n + j] : 0.0;
+    gring[slot] = load_or_zero(Rt + (j < n ? (int64_t)j * n + j : 0), j < n);
+  };
+  // consume row j from slot d, then refill the slot with row j + DEPTH (the
+  // refill is issued once the slot's values are dead, so that it lands in
+  // the same registers and nothing is moved at the loop's back edge)
+  auto step = [&](int j, int d) {
+    const double* row = ring[d];
+    const double gma = gring[d];
+    const int jq = j >> 6;
+    double v = ice.b[0];
+#pragma unroll
+    for (int q = 1; q < XPL; ++q)
+      if (q == jq) v = ice.b[q];
+    const double alpha = readlane_t(v, j & 63);
+    ice.bad |= !isfinite(gma) || !isfinite(alpha);
+    double sn, cs;
+    ice_step(ice.es2, ice.F, alpha, gma, LARGEST, sn, cs);
+#pragma unroll
+    for (int q = 0; q < XPL; ++q) ice.b[q] = fma(sn, ice.b[q], cs * row[q]);
+    load(j + DEPTH, d);
   };
 #pragma unroll
   for (int d = 0; d < DEPTH; ++d) load(1 + d, d);
-  for (int j0 = 1; j0 < n; j0 += DEPTH) {
+  // whole groups of DEPTH rows without branches (the loads stay in flight
+  // across iterations), then the remaining rows
+  int j0 = 1;
+  for (; j0 + DEPTH <= n; j0 += DEPTH) {
 #pragma unroll
-    for (int d = 0; d < DEPTH; ++d) {
-      const int j = j0 + d;
-      if (j < n) {
-        double row[XPL];
-#pragma unroll
-        for (int q = 0; q < XPL; ++q) row[q] = ring[d][q];
-        const double gma = gring[d];
-        load(j + DEPTH, d);
-        const int jq = j >> 6;
-        double v = ice.b[0];
-#pragma unroll
-        for (int q = 1; q < XPL; ++q)
-          if (q == jq) v = ice.b[q];
-        const double alpha = readlane_t(v, j & 63);
-        ice.bad |= !isfinite(gma) || !isfinite(alpha);
-        double sn, cs;
-        ice_step(ice.es2, ice.F, alpha, gma, LARGEST, sn, cs);
-#pragma unroll
-        for (int q = 0; q < XPL; ++q) ice.b[q] = fma(sn, ice.b[q], cs * row[q]);
-      }
-    }
+    for (int d = 0; d < DEPTH; ++d) step(j0 + d, d);
   }
+#pragma unroll
+  for (int d = 0; d < DEPTH; ++d)
+    if (j0 + d < n) step(j0 + d, d);
   return ice.estimate();
 }
 
