@@ -146,6 +146,21 @@ def test_wide_auto_escalates_like_the_oracle(M):
     assert MT.rel_diff(Rh, Rt) <= 50 * n * U64 * kappa
 
 
+@pytest.mark.parametrize("s,seed", [(201, 0), (204, 2)])
+def test_wide_posterior_rerun_ladder_matches_oracle(M, s, seed):
+    """n = 200 with a sketch barely taller than n: kappa(Rc) stays above the
+    posterior bound at every precision, so AUTO reruns the column-panel pass
+    at FP32, then FP64, and reports the posterior warning, as the oracle
+    does."""
+    A = W.test_matrix(2048, 200, 1e2, 3)
+    progress(f"wide posterior ladder s={s} seed={seed}")
+    Q, R, info = M.factor(to_dev(A), "auto", seed=seed, s=s)
+    o = OM.factor(A, OM.AUTO, seed, s=s)
+    assert (info.status, info.precision, info.escalations) == (o.status, "fp64", 2), (info, o.status)
+    assert abs(info.kappa_rc_est - o.kappa_rc) <= 1e-4 * o.kappa_rc
+    assert MT.residual(A, to_host(Q), to_host(R), 1.0) <= 1e-13
+
+
 def test_wide_fp64_sketch_factor_and_estimate_match_the_oracle(M):
     """FP64 sketch at n = 512, kappa = 1e12: the blocked Householder factor's
     condition estimate (ICE on Rs, kappa_rs_est) against the oracle's ICE on
