@@ -269,24 +269,44 @@ __global__ __launch_bounds__(GPR_THREADS, 2) void gram_pair_kernel(
 }
 
 // Sum of the chunk partials of every pair in fixed order; writes G_IJ and
-// its mirror G_JI.
-__global__ void gram_pair_reduce_kernel(const double* __restrict__ Gpart, int chunks, int n,
-                                        double* __restrict__ G, int64_t ldg, const Ctrl* __restrict__ ctrl,
-                                        int phase) {
+// its mirror G_JI. A workgroup of 4 waves takes 64 entries of one pair;
+// wave w sums its quarter of the chunks (8 loads in flight), and the four
+// quarter sums are added in order.
+__global__ __launch_bounds__(256) void gram_pair_reduce_kernel(const double* __restrict__ Gpart, int chunks, int n,
+                                                               double* __restrict__ G, int64_t ldg,
+                                                               const Ctrl* __restrict__ ctrl, int phase) {
   if (skip_launch(ctrl, P_AUTO, phase)) return;
+  __shared__ double part[4][64];
   const int pr = blockIdx.y;
   int I, J;
   pair_of(pr, n, I, J);
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= WD_PANEL * WD_PANEL) return;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int e = blockIdx.x * 64 + l;
+  const int per = (chunks + 3) / 4;
+  const int c0 = w * per, c1 = min(chunks, c0 + per);
+  double acc = 0.0;
+  if (e < WD_PANEL * WD_PANEL) {
+    const double* p = Gpart + (int64_t)pr * chunks * (WD_PANEL * WD_PANEL) + e;
+    constexpr int64_t str = WD_PANEL * WD_PANEL;
+    int c = c0;
+    for (; c + 8 <= c1; c += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = p[(int64_t)(c + u) * str];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    for (; c < c1; ++c) acc += p[(int64_t)c * str];
+  }
+  part[w][l] = acc;
+  __syncthreads();
+  if (w != 0 || e >= WD_PANEL * WD_PANEL) return;
   const int i = e % WD_PANEL, j = e / WD_PANEL;
   const int gi = WD_PANEL * I + i, gj = WD_PANEL * J + j;
   if (gi >= n || gj >= n) return;
-  const double* p = Gpart + (int64_t)pr * chunks * (WD_PANEL * WD_PANEL) + e;
-  double s = 0.0;
-  for (int c = 0; c < chunks; ++c) s += p[(int64_t)c * (WD_PANEL * WD_PANEL)];
-  G[gi + (int64_t)gj * ldg] = s;
-  G[gj + (int64_t)gi * ldg] = s;
+  const double sum = ((part[0][l] + part[1][l]) + part[2][l]) + part[3][l];
+  G[gi + (int64_t)gj * ldg] = sum;
+  G[gj + (int64_t)gi * ldg] = sum;
 }
 
 // Row chunks per pair: about 768 workgroups over all pairs (three per
@@ -325,7 +345,7 @@ hipError_t launch_gram_wide(const double* B, int m, int n, int64_t ldb, double* 
     const int chunks8 = (chunks + 7) / 8 * 8;
     hipLaunchKernelGGL(gram_pair_kernel, dim3(chunks8 * npr), dim3(GPR_THREADS), 0, st, B, m, n, ldb, chunks, rpc,
                        npr, Gpart_pairs, ctrl, phase);
-    hipLaunchKernelGGL(gram_pair_reduce_kernel, dim3((WD_PANEL * WD_PANEL + 255) / 256, npr), dim3(256), 0, st,
+    hipLaunchKernelGGL(gram_pair_reduce_kernel, dim3((WD_PANEL * WD_PANEL + 63) / 64, npr), dim3(256), 0, st,
                        (const double*)Gpart_pairs, chunks, n, G, ldg, ctrl, phase);
   }
   return hipGetLastError();
