@@ -27,7 +27,14 @@
  *   - `stream` is a hipStream_t (NULL = the legacy default stream); all
  *     work is enqueued asynchronously on it; no entry point waits for the
  *     device, except mrcqr_factor_batched (blocking argument copy) and
- *     mrcqr_release_cache;
+ *     mrcqr_release_cache. A fixed-precision factorization with n > 128
+ *     (mrcqr_factor, mrcqr_execute) runs its posterior check on a second
+ *     stream that the library keeps per (device, stream), forked from
+ *     `stream` after Rc^{-1} and joined back before the info is written,
+ *     so that it overlaps the product Q = B Rc^{-1}; work enqueued on
+ *     `stream` after the call is ordered after all of it (under stream
+ *     capture both become graph nodes; a stream first seen under capture
+ *     takes the serial sequence);
  *   - argument errors are returned synchronously (MRCQR_ERR_ARG /
  *     MRCQR_ERR_UNSUPPORTED) before anything is launched; numeric outcomes
  *     (non-finite sketch, Cholesky breakdown, singular sketch, posterior

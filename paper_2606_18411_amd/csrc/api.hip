@@ -171,8 +171,43 @@ static void plan_layout(mrcqr_plan* p) {
   p->total = o;
 }
 
+// A second stream per (device, caller stream) for the posterior check of a
+// fixed-precision call with n > 128: there the check (two launches per
+// power step over many workgroups) decides nothing that the product
+// Q = B Rc^{-1} depends on (no rerun), so it runs beside the product
+// (fork after Rc^{-1}, join before the info is written). Created on the
+// first call from a stream that is not being captured and kept for the
+// process; calls under capture without one take the serial sequence.
+struct SideStream {
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+static std::mutex g_side_mu;
+static std::map<std::pair<int, hipStream_t>, SideStream> g_side;
+
+static const SideStream* side_stream_for(hipStream_t st) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(g_side_mu);
+  auto key = std::make_pair(dev, st);
+  auto it = g_side.find(key);
+  if (it != g_side.end()) return &it->second;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
+  SideStream ss;
+  if (hipStreamCreateWithFlags(&ss.side, hipStreamNonBlocking) != hipSuccess) return nullptr;
+  if (hipEventCreateWithFlags(&ss.fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ss.join, hipEventDisableTiming) != hipSuccess) {
+    if (ss.fork) (void)hipEventDestroy(ss.fork);
+    (void)hipStreamDestroy(ss.side);
+    return nullptr;
+  }
+  return &g_side.emplace(key, ss).first->second;
+}
+
 static int execute(const mrcqr_plan* p, char* ws, const double* A, int64_t lda, int prec, uint64_t seed,
-                   double* Q, int64_t ldq, double* R, int64_t ldr, hipStream_t st, mrcqr_info* info) {
+                   double* Q, int64_t ldq, double* R, int64_t ldr, hipStream_t st, mrcqr_info* info,
+                   bool allow_fork = true) {
   const int m = (int)p->m, n = (int)p->n, s = (int)p->s;
   Ctrl* ctrl = reinterpret_cast<Ctrl*>(ws + p->off_ctrl);
   int32_t* S = reinterpret_cast<int32_t*>(ws + p->off_S);
@@ -209,7 +244,15 @@ static int execute(const mrcqr_plan* p, char* ws, const double* A, int64_t lda, 
   };
   // Stage 2 and 3 of one pass; Q is formed in the pass's tail phase, which
   // is skipped when the posterior check asks for a rerun
-  auto stage2 = [&](int phase, int tail_phase) -> bool {
+  // side: the posterior check runs there beside Q (fixed precision only)
+  auto stage2 = [&](int phase, int tail_phase, const SideStream* side = nullptr) -> bool {
+    const hipStream_t pst = side ? side->side : st;
+    auto fork = [&]() -> bool {
+      return !side || (hipEventRecord(side->fork, st) == hipSuccess && hipStreamWaitEvent(pst, side->fork, 0) == hipSuccess);
+    };
+    auto join = [&]() -> bool {
+      return !side || (hipEventRecord(side->join, pst) == hipSuccess && hipStreamWaitEvent(st, side->join, 0) == hipSuccess);
+    };
     if (n > NSTEP)
       return launch_trsm_wide(A, m, n, lda, Rs, n, B, ldb, Tw, ctrl, phase, st) == hipSuccess &&
              launch_gram_wide(B, m, n, ldb, Gpart, reinterpret_cast<double*>(ws + p->off_Gpair), G, n, ctrl, phase,
@@ -217,16 +260,16 @@ static int execute(const mrcqr_plan* p, char* ws, const double* A, int64_t lda, 
              launch_cholesky_wide(G, n, n, Rc, n, nullptr, nullptr, reinterpret_cast<double*>(ws + p->off_T),
                                   reinterpret_cast<int32_t*>(ws + p->off_fails),
                                   reinterpret_cast<double*>(ws + p->off_Gpair), Tw, ctrl, phase, st) == hipSuccess &&
-             launch_rc_tail_wide(Rc, n, n, Rs, n, Rci, n, R, ldr, ctrl, phase, st) == hipSuccess &&
+             launch_rc_tail_wide(Rc, n, n, Rs, n, Rci, n, R, ldr, ctrl, phase, st) == hipSuccess && fork() &&
              launch_posterior_wide(Rc, Rci, n, n, reinterpret_cast<double*>(ws + p->off_T), ctrl, phase, nullptr,
-                                   st) == hipSuccess &&
-             launch_qform_wide(B, m, n, ldb, Rci, n, Q, ldq, ctrl, tail_phase, st) == hipSuccess;
+                                   pst) == hipSuccess &&
+             launch_qform_wide(B, m, n, ldb, Rci, n, Q, ldq, ctrl, tail_phase, st) == hipSuccess && join();
     return launch_trsm(A, m, n, lda, Rs, n, B, ldb, Tw, ctrl, phase, st) == hipSuccess &&
            launch_gram(B, m, n, ldb, Gpart, G, n, ctrl, phase, st) == hipSuccess &&
            launch_cholesky(G, n, n, Rc, n, nullptr, nullptr, ctrl, phase, st) == hipSuccess &&
-           launch_rc_tail(Rc, n, n, Rs, n, Rci, n, R, ldr, ctrl, phase, st) == hipSuccess &&
-           launch_posterior(Rc, Rci, n, n, ctrl, phase, nullptr, st) == hipSuccess &&
-           launch_qform(B, m, n, ldb, Rci, n, Q, ldq, ctrl, tail_phase, st) == hipSuccess;
+           launch_rc_tail(Rc, n, n, Rs, n, Rci, n, R, ldr, ctrl, phase, st) == hipSuccess && fork() &&
+           launch_posterior(Rc, Rci, n, n, ctrl, phase, nullptr, pst) == hipSuccess &&
+           launch_qform(B, m, n, ldb, Rci, n, Q, ldq, ctrl, tail_phase, st) == hipSuccess && join();
   };
   if (automode) {
     for (int pp : {P_FP16, P_FP32, P_FP64})
@@ -241,7 +284,10 @@ static int execute(const mrcqr_plan* p, char* ws, const double* A, int64_t lda, 
     if (!stage2(PH_RERUN2, PH_RERUN2)) return MRCQR_ERR_DEVICE;
   } else {
     if (!stage1(prec, PH_FIRST)) return MRCQR_ERR_DEVICE;
-    if (!stage2(PH_FIRST, PH_FIRST)) return MRCQR_ERR_DEVICE;
+    // n <= 128: the check is one workgroup and the product fills every
+    // compute unit, so the fork gains nothing there (measured)
+    if (!stage2(PH_FIRST, PH_FIRST, allow_fork && n > NSTEP ? side_stream_for(st) : nullptr))
+      return MRCQR_ERR_DEVICE;
   }
   if (info && (e = launch_ctrl_finalize(ctrl, info, st)) != hipSuccess) return MRCQR_ERR_DEVICE;
   return MRCQR_OK;
@@ -563,8 +609,9 @@ int mrcqr_factor_noalloc(const double* A, int64_t m, int64_t n, int64_t lda, int
   if (!ws) return MRCQR_ERR_DEVICE;
   // Nothing in the workspace has to start at zero: the draw kernel resets
   // the control block, and every partial sum is written before it is read.
+  // the serial sequence: no side stream or events are created here
   return execute(&plan, static_cast<char*>(ws), A, lda, sketch_precision, seed, Q, ldq, R, ldr, as_stream(stream),
-                 info_dev);
+                 info_dev, false);
 }
 
 size_t mrcqr_factor_noalloc_max_workspace_bytes(void) { return NOALLOC_SCRATCH_BYTES; }

@@ -21,7 +21,7 @@ def M():
 
 
 # n = 256 takes the column-panel path (its launch sequence is as static)
-@pytest.mark.parametrize("precision,n", [("auto", 64), ("fp16", 64), ("auto", 256)])
+@pytest.mark.parametrize("precision,n", [("auto", 64), ("fp16", 64), ("auto", 256), ("fp16", 256)])
 def test_graph_replays_match_eager_calls(M, precision, n):
     m, seed = 1 << 14, 21
     progress(f"graph capture {precision} n={n}")
