@@ -105,6 +105,39 @@ def test_plan_workspace_layout_is_sane(lib):
     assert lib.mrcqr_plan_create(10, 20, 0, ctypes.byref(p)) == 1
 
 
+def test_column_panel_shapes_and_workspaces(lib):
+    """128 < n <= 512: accepted with s <= 1024 (the blocked sketch QR), with
+    workspaces that hold B plus the n x n objects, the pair-Gram partials and
+    the row-major copies for the condition estimates."""
+    i64, vp, sz = ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t
+    p = ctypes.c_void_p()
+    lib.mrcqr_plan_create.argtypes = [i64, i64, i64, ctypes.POINTER(vp)]
+    lib.mrcqr_plan_workspace_bytes.restype = sz
+    lib.mrcqr_plan_workspace_bytes.argtypes = [vp]
+    lib.mrcqr_plan_destroy.argtypes = [vp]
+    m = 1 << 20
+    for n in (129, 256, 300, 512):
+        assert lib.mrcqr_plan_create(m, n, 0, ctypes.byref(p)) == 0, n
+        b = lib.mrcqr_plan_workspace_bytes(p)
+        assert m * n * 8 + 4 * n * n * 8 < b < m * n * 8 * 1.5, (n, b)
+        lib.mrcqr_plan_destroy(p)
+    assert lib.mrcqr_plan_create(m, 300, 1024, ctypes.byref(p)) == 0
+    lib.mrcqr_plan_destroy(p)
+    assert lib.mrcqr_plan_create(m, 300, 1025, ctypes.byref(p)) == 8  # sketch beyond the blocked QR
+    assert lib.mrcqr_plan_create(m, 513, 0, ctypes.byref(p)) == 8
+    assert lib.mrcqr_plan_create(400, 300, 0, ctypes.byref(p)) == 1  # s = 2n > m
+    for name, args in (("mrcqr_trsm_workspace_bytes", (512,)), ("mrcqr_gram_workspace_bytes", (m, 512))):
+        f = getattr(lib, name)
+        f.restype = sz
+        f.argtypes = [i64] * len(args)
+        assert f(*args) > 0, name
+    lib.mrcqr_gram_workspace_bytes.restype = sz
+    assert lib.mrcqr_gram_workspace_bytes(m, 513) == 0
+    lib.mrcqr_posterior_workspace_bytes.restype = sz
+    lib.mrcqr_posterior_workspace_bytes.argtypes = [i64]
+    assert lib.mrcqr_posterior_workspace_bytes(600) == 0  # nothing beyond n = 512
+
+
 def test_batch_and_regime_argument_errors(lib):
     """The batch plan rejects bad member shapes, and the batch and regime
     entry points reject missing arguments, before any device call."""
