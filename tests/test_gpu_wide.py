@@ -128,6 +128,23 @@ def test_wide_factor_matches_unique_qr(M, m, n, prec):
         assert info.precision == "fp16" and info.escalations == 0
 
 
+# edges of the column-panel path: n just above 128, ragged last panels
+# (n = 129, 300, 511), the sketch as tall as A (s = 2n = m), few row chunks
+@pytest.mark.parametrize("m,n", [(258, 129), (600, 300), (1100, 511), (5000, 129)])
+@pytest.mark.parametrize("prec", ["fp64", "fp16"])
+def test_wide_edge_shapes(M, m, n, prec):
+    kappa = 1e2
+    A, U, Qt, Rt = _problem(m, n, kappa, 60 + n)
+    progress(f"wide edge m={m} n={n} {prec}")
+    Q, R, info = M.factor(to_dev(A), prec, seed=5)
+    assert info.status == 0, info
+    Qh, Rh = to_host(Q), to_host(R)
+    assert MT.orthogonality(Qh) <= 1e-13
+    assert MT.residual(A, Qh, Rh, 1.0) <= 1e-13
+    assert MT.rel_diff(Rh, Rt) <= 50 * n * U64 * kappa
+    assert np.all(np.tril(Rh, -1) == 0) and np.all(np.diag(Rh) > 0)
+
+
 def test_wide_auto_escalates_like_the_oracle(M):
     """kappa = 1e6 at n = 256: the FP16 attempt's condition estimate on the
     blocked Householder factor crosses 1e4 and AUTO lands on FP32, as the
