@@ -142,10 +142,105 @@ __global__ __launch_bounds__(GP_THREADS, 4) void gemm_panel_kernel(
   }
 }
 
+// The same product for K <= 128 with all of W (128 KB at K = 128) staged
+// once in LDS for the whole kernel, in A-operand order: no restaging per
+// pass and no barrier after the staging; 16 waves per workgroup, one
+// workgroup per CU (each wave's stores overlap the other waves' products).
+// Chunks, k-steps and column blocks are taken in the order of
+// gemm_panel_kernel, so both give the same sums.
+constexpr int GRS_THREADS = 1024;
+constexpr int GRS_ROWS = (GRS_THREADS / 64) * 16;  // 256 rows per pass
+constexpr int GRS_KMAX = 128;
+
+template <bool TW>
+__global__ __launch_bounds__(GRS_THREADS, 4) void gemm_resident_kernel(
+    const double* __restrict__ Bs, int64_t ldb, int K, int kvalid, const double* __restrict__ W, int64_t ldw,
+    const double* C0, int64_t ldc0, double* C, int64_t ldc, int rows, int nc, double alpha, double beta,
+    const Ctrl* __restrict__ ctrl, int phase) {
+  extern __shared__ __attribute__((aligned(16))) double Wl[];  // (K/4) k-steps x 8 blocks x 64
+  if (skip_launch(ctrl, P_AUTO, phase)) return;
+  const int tid = threadIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63, g = l >> 4, c16 = l & 15;
+  const int nks = (K + 3) / 4;  // k-steps of 4
+  const int nch4 = (nks + 3) / 4 * 4;  // k-steps staged (whole chunks, zero past kvalid)
+  // stage W: entry (ks, b, lane) = W(4 ks + lane / 16, 16 b + lane % 16)
+  for (int e = tid; e < nch4 * 512; e += GRS_THREADS) {
+    const int ks = e >> 9, b = (e >> 6) & 7, ll = e & 63;
+    const int k = 4 * ks + (ll >> 4), j = 16 * b + (ll & 15);
+    double v = 0.0;
+    if (j < nc && k < kvalid) v = TW ? W[j + (int64_t)k * ldw] : W[k + (int64_t)j * ldw];
+    Wl[e] = v;
+  }
+  __syncthreads();
+  const double* Bl = Bs + c16 + (int64_t)g * ldb;
+  const double* C0l = C0 + c16 + (int64_t)g * ldc0;
+  double* Cl = C + c16 + (int64_t)g * ldc;
+  const int nch = (nks + 3) / 4;  // chunks of 4 k-steps (16 k)
+  for (int64_t pan = blockIdx.x; pan * GRS_ROWS < rows; pan += gridDim.x) {
+    const int64_t r0 = pan * GRS_ROWS + 16 * w;
+    const bool row_in = r0 + c16 < rows;
+    f64x4 acc[8];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) acc[b] = f64x4{0.0, 0.0, 0.0, 0.0};
+    double bd[4];
+    auto loadb = [&](int c) {
+      int64_t u = r0 + (int64_t)(16 * c) * ldb;
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        asm volatile("" : "+s"(u));
+        const bool in = row_in && 16 * c + 4 * ks + g < kvalid;
+        bd[ks] = in ? __builtin_nontemporal_load(&Bl[u]) : 0.0;
+        u += 4 * ldb;
+      }
+    };
+    loadb(0);
+    for (int c = 0; c < nch; ++c) {
+      double cur[4];
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) cur[ks] = bd[ks];
+      if (c + 1 < nch) loadb(c + 1);
+      const double* Wc = Wl + (size_t)(16 * c) * 128;  // 4 k-steps x 512 entries
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+        for (int b = 0; b < 8; ++b) acc[b] = mfma_f64(Wc[(ks * 8 + b) * 64 + l], cur[ks], acc[b]);
+    }
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int64_t uc = r0 + (int64_t)(16 * b + 4 * r) * ldc, u0 = r0 + (int64_t)(16 * b + 4 * r) * ldc0;
+        asm volatile("" : "+s"(uc), "+s"(u0));
+        const bool in = row_in && 16 * b + 4 * r + g < nc;
+        if (in) {
+          double v = alpha * acc[b][r];
+          if (beta != 0.0) v = fma(beta, __builtin_nontemporal_load(&C0l[u0]), v);
+          __builtin_nontemporal_store(v, &Cl[uc]);
+        }
+      }
+  }
+}
+
 hipError_t launch_gemm_panel(bool tw, const double* Bs, int64_t ldb, int K, int kvalid, const double* W, int64_t ldw,
                              const double* C0, int64_t ldc0, double* C, int64_t ldc, int rows, int nc, double alpha,
                              double beta, const Ctrl* ctrl, int phase, hipStream_t st) {
   if (nc < 1 || nc > 128 || rows < 1 || K < 1) return hipErrorInvalidValue;
+  if (K <= GRS_KMAX) {
+    const int nch = ((K + 3) / 4 + 3) / 4;
+    const size_t lds = (size_t)nch * 4 * 512 * sizeof(double);
+    const int64_t passes = ((int64_t)rows + GRS_ROWS - 1) / GRS_ROWS;
+    const dim3 grid((unsigned)(passes < 256 ? passes : 256)), block(GRS_THREADS);
+    if (tw) {
+      allow_dynamic_lds((const void*)gemm_resident_kernel<true>, lds);
+      hipLaunchKernelGGL(gemm_resident_kernel<true>, grid, block, lds, st, Bs, ldb, K, kvalid, W, ldw, C0, ldc0, C,
+                         ldc, rows, nc, alpha, beta, ctrl, phase);
+    } else {
+      allow_dynamic_lds((const void*)gemm_resident_kernel<false>, lds);
+      hipLaunchKernelGGL(gemm_resident_kernel<false>, grid, block, lds, st, Bs, ldb, K, kvalid, W, ldw, C0, ldc0, C,
+                         ldc, rows, nc, alpha, beta, ctrl, phase);
+    }
+    return hipGetLastError();
+  }
   const int64_t panels = ((int64_t)rows + GP_ROWS - 1) / GP_ROWS;
   const int64_t cap = 512;
   const dim3 grid((unsigned)(panels < cap ? panels : cap)), block(GP_THREADS);
