@@ -1,24 +1,27 @@
-// The path for 128 < n <= 512 on column panels of 128 (64 for the sketch
-// QR) or 32: every n x n object of the path outgrows one workgroup's registers
-// and LDS, so each step is taken panel by panel with the kernels of the
-// n <= 128 path plus the ones here.
+// The path for 128 < n <= 512 on column panels of 128 (32 or 64 for the
+// sketch QR): every n x n object of the path outgrows one workgroup's
+// registers and LDS, so each step is taken panel by panel with the kernels
+// of the n <= 128 path plus the ones here.
 //   Sketch QR (Algorithm 2, SketchQR): blocked Householder QR in the
-//     sketch's QR precision; a panel of 64 columns is factored by one
+//     sketch's QR precision; a panel of 32 or 64 columns is factored by one
 //     workgroup (LAPACK geqr2 order, reflectors left in place below the
-//     diagonal), its reflectors are applied to the columns to its right,
-//     and the finish kernel takes R (rows with a negative pivot flipped),
-//     the checks and the condition estimate of Rs.
+//     diagonal), its reflectors are applied to the columns to its right
+//     from LDS, and upper_copy_kernel and the finish kernel take R (rows
+//     with a negative pivot flipped), the checks and the condition
+//     estimate of Rs.
 //   B = A Rs^{-1} (Stage 2): per 128-column panel P, the update
-//     C = A_P - B_{<P} Rs_{<P,P} (gemm_panel_kernel) and the solve of the
-//     n <= 128 path with the diagonal panel, in place.
+//     C = A_P - B_{<P} Rs_{<P,P} (gemm_resident_kernel for K = 128,
+//     gemm_panel_kernel beyond) and the solve of the n <= 128 path with the
+//     diagonal panel, in place.
 //   G = B^T B (Algorithm 1 step 1): the diagonal 128 x 128 blocks by the
 //     n <= 128 Gram kernels, the blocks above them by gram_pair_kernel.
 //   G = Rc^T Rc (Algorithm 1 step 2): right-looking over 128-column panels:
 //     the n <= 128 Cholesky of the diagonal block, the panel
 //     X = G_{rest,P} Rc_PP^{-1} by the solve, Rc_{P,rest} = X^T, and the
-//     trailing update G_{rest,rest} -= X X^T (gemm_panel_kernel).
-//   X = Rc^{-1}, R = Rc Rs, the posterior power steps and Q = B X, each for
-//     n <= 512.
+//     trailing update G_{rest,rest} -= X X^T (the panel GEMM).
+//   X = Rc^{-1}, R = Rc Rs, the posterior power steps (many workgroups, two
+//     launches per step) and Q = B X (the panel GEMM per panel of Q), each
+//     for n <= 512.
 // Every kernel is gated by the control block like the n <= 128 ones.
 #include "batch.hpp"
 #include "ice.hpp"
