@@ -56,6 +56,42 @@ def test_wide_sketch_matches_definition(M, prec, m, n):
     assert np.max(err) <= 0, f"max excess {np.max(err):.3e}"
 
 
+# the paper's real-DFT operator at n > 128 (c = 3n = 768 bins from
+# {0..m/2}, three sketch-row blocks; m = 2^14 takes the remapped grid)
+@pytest.mark.parametrize("prec", [P.FP64, P.FP16])
+@pytest.mark.parametrize("m,n", [(16384, 256), (5003, 200)])
+def test_wide_rfft_sketch_matches_definition(M, prec, m, n):
+    c, seed = 3 * n, 9 + n
+    progress(f"wide rfft sketch {P.NAMES[prec]} m={m} n={n} c={c}")
+    A = W.test_matrix(m, n, 1e4, 6)
+    S = rng.sample_rows(seed, m // 2 + 1, c)
+    d = rng.signs(seed, m)
+    Y = to_host(M.sketch(to_dev(A), torch.from_numpy(S.astype(np.int32)).cuda(), seed, P.NAMES[prec],
+                         transform="rfft"))
+    Yo = SK.sketch_rfft(A, S, d, prec)
+    bound = SK.sketch_rfft_abs_bound(A, S, d, prec)
+    err = np.abs(Y - Yo) - (SKETCH_TOL[prec] * bound + (U32 * np.abs(Yo) if prec != P.FP64 else 0))
+    assert np.max(err) <= 0, f"max excess {np.max(err):.3e}"
+
+
+@pytest.mark.parametrize("prec", ["fp16", "fp64", "auto"])
+def test_wide_rfft_factor_matches_unique_qr(M, prec):
+    m, n, kappa = 4099, 256, 1e3
+    A, U, Qt, Rt = _problem(m, n, kappa, 50 + n)
+    progress(f"wide rfft factor {prec}")
+    plan = M.Plan(m, n, transform="rfft")
+    Q, R = M.empty_colmajor(m, n), M.empty_colmajor(n, n)
+    plan.execute(to_dev(A), Q, R, prec, seed=3)
+    torch.cuda.synchronize()
+    info = plan.last_info()
+    o = OM.factor(A, {"fp16": P.FP16, "fp64": P.FP64, "auto": OM.AUTO}[prec], 3, transform=OM.RFFT)
+    assert (info.status, info.precision_used, info.escalations) == (o.status, o.precision_used, o.escalations)
+    assert info.status == 0, info
+    Qh, Rh = to_host(Q), to_host(R)
+    assert MT.orthogonality(Qh) <= 1e-13 and MT.residual(A, Qh, Rh, 1.0) <= 1e-13
+    assert MT.rel_diff(Rh, Rt) <= 50 * n * U64 * kappa
+
+
 @pytest.mark.parametrize("m,n,kappa", [(3001, 256, 1e6), (1200, 200, 1e4), (5003, 512, 1e8)])
 def test_wide_trsm_matches_substitution(M, m, n, kappa):
     progress(f"wide trsm m={m} n={n} kappa={kappa:g}")
