@@ -26,15 +26,17 @@ def _run(M, plan, A, precision, seed):
     return Q, R, plan.last_info()
 
 
-def test_carry_sequence_matches_oracle(M):
-    m, n, seed = 1 << 15, 64, 31
+# n = 256 takes the column-panel path, which carries the record the same way
+@pytest.mark.parametrize("m,n", [(1 << 15, 64), (4096, 256)])
+def test_carry_sequence_matches_oracle(M, m, n):
+    seed = 31
     # clear of the regime bounds: kappa 1e2 -> FP16, 1e6 -> FP32, 1e10 -> FP64
     kappas = [1e2, 1e6, 1e2, 1e10, 1e6, 1e2]
     plan = M.Plan(m, n)
     start = P.FP16
     seen = []
     for i, k in enumerate(kappas):
-        progress(f"carry call {i} kappa={k:g}")
+        progress(f"carry call {i} n={n} kappa={k:g}")
         A = W.test_matrix(m, n, k, 700 + i)
         Q, R, g = _run(M, plan, to_dev(A), "auto_carry", seed)
         o = OM.factor(A, OM.AUTO, seed=seed, start=start)
