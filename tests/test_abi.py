@@ -138,6 +138,25 @@ def test_column_panel_shapes_and_workspaces(lib):
     assert lib.mrcqr_posterior_workspace_bytes(600) == 0  # nothing beyond n = 512
 
 
+def test_noalloc_entry_rejects_shapes_beyond_its_array_synchronously(lib):
+    """The no-allocation entry point answers MRCQR_ERR_WORKSPACE, before any
+    device call, for shapes whose plan outgrows its fixed device array (every
+    column-panel shape at m = 2^20), and MRCQR_ERR_ARG for bad arguments."""
+    i64, vp = ctypes.c_int64, ctypes.c_void_p
+    f = lib.mrcqr_factor_noalloc
+    f.argtypes = [vp, i64, i64, i64, ctypes.c_int, ctypes.c_uint64, i64, vp, i64, vp, i64, vp, vp]
+    lib.mrcqr_factor_noalloc_max_workspace_bytes.restype = ctypes.c_size_t
+    cap = lib.mrcqr_factor_noalloc_max_workspace_bytes()
+    assert cap >= 1 << 20
+    a, q, r = vp(0x1000), vp(0x2000), vp(0x3000)
+    m = 1 << 20
+    for n in (128, 256, 512):
+        assert m * n * 8 > cap
+        assert f(a, m, n, m, 3, 0, 0, q, m, r, n, None, None) == 5, n
+    assert f(a, m, 600, m, 3, 0, 0, q, m, r, 600, None, None) == 8
+    assert f(None, m, 256, m, 3, 0, 0, q, m, r, 256, None, None) == 1
+
+
 def test_batch_and_regime_argument_errors(lib):
     """The batch plan rejects bad member shapes, and the batch and regime
     entry points reject missing arguments, before any device call."""
